@@ -1,0 +1,21 @@
+"""Loose statistical sanity checks of the dynamics (not parity): KPZ power-law
+roughening for p > 0 = q (Sec. I-A), with growth exponent beta near 0.24 in
+2+1 dimensions."""
+import numpy as np
+import pytest
+
+
+@pytest.mark.slow
+def test_kpz_growth_exponent(orc):
+    L = 512
+    st = orc.flat(L, L, track_heights=False)
+    ts, w2 = [], []
+    t = 0
+    for target in [16, 23, 32, 45, 64, 91, 128, 181, 256]:
+        orc.run(st, target - t, 0.75, 0.0, seed=20160601)
+        t = target
+        ts.append(t)
+        w2.append(orc.moments(st)[3])
+    slope = np.polyfit(np.log(ts), np.log(w2), 1)[0]
+    # 2 beta ~ 0.48; generous band for a single small realization
+    assert 0.36 <= slope <= 0.60, slope
