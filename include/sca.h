@@ -1,0 +1,151 @@
+/*
+ * sca.h -- C ABI of the bit-vectorized checkerboard SCA of the 2+1-dimensional
+ * octahedron surface-growth model on AMD Instinct MI355X (gfx950).
+ *
+ * Model (Kelling, Odor, Gemming 2016, Sec. I-A and Eq. (2)): an X x Y
+ * periodic lattice of heights whose neighbours differ by exactly 1, stored as
+ * two slope bits per site (Sec. II-A).  A half-step updates one checkerboard
+ * sublattice at once: a local minimum is lifted by 2 with probability p, a
+ * local maximum lowered by 2 with probability q, each flipping its four
+ * slope bits.  One Monte-Carlo step (MCS) is the even half-step ((x+y) even)
+ * followed by the odd one.
+ *
+ * Device state layout (Sec. II-A, role-grouped arrays; Fig. 3 of the paper
+ * keeps one array per slope direction and sublattice):
+ *   uint64 S[2][2][Y][W],  W = max(1, X/128)
+ *   S[d][pi][y][w]: d = 0 x-slopes, d = 1 y-slopes; pi = (x+y)&1; bit b of
+ *   word w holds the site x with x>>1 == 64*w + b of row y.  A set bit means
+ *   the height rises by one towards the site across that bond from the
+ *   left (x) or lower (y) neighbour.  For X < 128 only bits 0..X/2-1 are used
+ *   and the rest are zero.  In torch terms: an int64 tensor of shape
+ *   (2, 2, Y, W).
+ *
+ * Random acceptance words (counter-based, so results are reproducible and
+ * independent of the launch shape): Philox4x32-10 with key
+ * (seed mod 2^32, seed >> 32) and counter (g, t, 2j + pi, 0), where
+ * g = y*W + w is the canonical word, t the 0-based MCS index and j the call
+ * index within the word.  Dyadic p and q (p*2^32 and q*2^32 integers;
+ * Sec. III: sums of powers 1/2^i via and/or) fold n = max(n_p, n_q) 64-bit
+ * draws, least significant binary digit first; any other p or q compares one
+ * 32-bit uniform per site with floor(r * 2^32) (Sec. II-B), 16 calls per word.
+ *
+ * Conventions for every call:
+ *  - Sizes: X and Y powers of two, 4 <= X, Y <= 131072.  0 <= p, q <= 1.
+ *  - Ownership: every device buffer is owned by the caller; the library keeps
+ *    non-owning pointers, so the caller keeps them alive until sca_destroy.
+ *    The library owns only a small device workspace (about 40*Y bytes)
+ *    allocated by sca_init and freed by sca_destroy.
+ *  - Streams: all work is enqueued on the stream given to sca_init.  Only
+ *    calls that return numbers to the host synchronize that stream.
+ *  - Errors: functions return SCA_OK or a negative code; an invalid argument
+ *    leaves the state untouched.  After any HIP failure the context is
+ *    failed and every later call returns SCA_ESTATE.
+ *  - A context is not thread-safe; contexts do not share state.
+ */
+#ifndef SCA_H
+#define SCA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sca_ctx sca_ctx;
+
+enum sca_status {
+    SCA_OK = 0,
+    SCA_EINVAL = -1,    /* invalid argument; nothing was changed */
+    SCA_ENOMEM = -2,    /* device allocation failed */
+    SCA_EDEVICE = -3,   /* a HIP call failed; the context is now failed */
+    SCA_EOVERFLOW = -4, /* an exact result does not fit its output type */
+    SCA_ESTATE = -5,    /* the context failed earlier */
+    SCA_EBUSY = -6      /* a capacity limit was reached (batched calls) */
+};
+
+/* sca_step_ex flags */
+#define SCA_FORCE_PERSITE 1u /* use per-site 32-bit compares even for dyadic p, q */
+
+/* Length of the caller-owned int64 aux buffer; aux[0] holds h(0,0). */
+#define SCA_AUX_LEN 8
+
+/* Number of uint64 words of S for an X x Y lattice: 4 * Y * max(1, X/128);
+ * 0 for invalid sizes. */
+size_t sca_state_words(int64_t X, int64_t Y);
+
+/* Creates a context for an X x Y lattice and writes the flat initial surface
+ * h(x,y) = (x+y)&1 (every even site a minimum: S[.][0] = 0, S[.][1] = all
+ * valid bits), h(0,0) = 0, t = 0.
+ *   slopes_dev: device buffer of sca_state_words(X,Y) uint64 (S above)
+ *   aux_dev:    device buffer of SCA_AUX_LEN int64
+ *   hip_stream: hipStream_t to enqueue on (NULL = default stream)
+ * The initialisation is enqueued, not waited for. */
+int sca_init(sca_ctx** out, int64_t X, int64_t Y, uint64_t seed, void* slopes_dev,
+             int64_t* aux_dev, void* hip_stream);
+
+/* Advances n_mcs >= 0 MCS with deposition probability p and removal
+ * probability q (Eq. (2)); each MCS is the even then the odd half-step
+ * (Sec. I-A), t grows by n_mcs.  Asynchronous. */
+int sca_step(sca_ctx* ctx, int64_t n_mcs, double p, double q);
+
+/* sca_step with flags (SCA_FORCE_PERSITE). */
+int sca_step_ex(sca_ctx* ctx, int64_t n_mcs, double p, double q, unsigned flags);
+
+/* Heights h(x,y) of rows [y0, y0+ny), all x, row-major int32 into out_dev
+ * (ny*X values, caller-owned):
+ *   h(x,y) = h(0,0) + sum_{j=1..y} (2 sy(0,j) - 1) + sum_{i=1..x} (2 sx(i,y) - 1).
+ * SCA_EOVERFLOW if |h(0,0)| + X + Y >= 2^31.  Synchronizes (reads h(0,0)). */
+int sca_heights(sca_ctx* ctx, int64_t y0, int64_t ny, int32_t* out_dev);
+
+/* Exact moments of the height field: out3 = {N, sum h, sum h^2} with
+ * N = X*Y, and w2 = (N sum h^2 - (sum h)^2) / N^2, the squared surface
+ * roughness (Sec. I-A).  Sums are formed exactly in 128-bit arithmetic;
+ * SCA_EOVERFLOW if one does not fit in int64.  Synchronizes. */
+int sca_roughness(sca_ctx* ctx, int64_t out3[3], double* w2);
+
+/* Bytes of a snapshot: the state S plus one int64 h(0,0). */
+size_t sca_snapshot_bytes(const sca_ctx* ctx);
+
+/* Copies S and h(0,0) into the caller-owned device buffer snap_dev
+ * (sca_snapshot_bytes bytes).  Asynchronous. */
+int sca_snapshot(sca_ctx* ctx, void* snap_dev);
+
+/* Two-time sums between the current heights h_t and those of a snapshot h_s
+ * taken earlier from a context of the same size (the aging studies the paper
+ * names as its application, Sec. IV): out4 = {N, sum h_t h_s, sum h_t,
+ * sum h_s}, exact; c_ts = (N sum h_t h_s - sum h_t sum h_s) / N^2.
+ * SCA_EOVERFLOW if a sum does not fit in int64.  Synchronizes. */
+int sca_autocorr(sca_ctx* ctx, const void* snap_dev, int64_t out4[4], double* c_ts);
+
+/* Current MCS count t and origin height h(0,0).  Synchronizes. */
+int sca_get_meta(sca_ctx* ctx, int64_t* t, int64_t* h0);
+
+/* Sets the MCS counter (for resuming from a saved state; the caller restores
+ * S and aux itself).  0 <= t < 2^32. */
+int sca_set_time(sca_ctx* ctx, int64_t t);
+
+/* Test hook: one half-step of sublattice `parity` whose acceptance words are
+ * read from xi_p_dev[g], xi_q_dev[g] (Y*W uint64 each, device) instead of the
+ * random stream; t is not advanced.  Asynchronous. */
+int sca_debug_halfstep(sca_ctx* ctx, int parity, const uint64_t* xi_p_dev,
+                       const uint64_t* xi_q_dev);
+
+/* Test hook: the device Philox4x32-10 block function for n counters
+ * ctr_dev[4i..4i+3] with key (k0, k1) into out_dev[4i..4i+3].  Asynchronous
+ * on hip_stream. */
+int sca_debug_philox(const uint32_t* ctr_dev, uint32_t k0, uint32_t k1, int64_t n,
+                     uint32_t* out_dev, void* hip_stream);
+
+/* Frees the context and its workspace (after synchronizing its stream).
+ * Never frees caller buffers.  NULL is ignored. */
+void sca_destroy(sca_ctx* ctx);
+
+/* Static description of a status code. */
+const char* sca_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SCA_H */

@@ -1,0 +1,76 @@
+"""ctypes binding of libsca.so (include/sca.h): argument marshalling only.
+
+The library is loaded after torch so that both use the same HIP runtime.  There
+is no fallback: if libsca.so is missing or fails to load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # noqa: F401  (loads the HIP runtime the library links against)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsca.so")
+
+SCA_OK, SCA_EINVAL, SCA_ENOMEM, SCA_EDEVICE, SCA_EOVERFLOW, SCA_ESTATE, SCA_EBUSY = 0, -1, -2, -3, -4, -5, -6
+SCA_FORCE_PERSITE = 1
+SCA_AUX_LEN = 8
+
+
+class ScaError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {_strerror(code)} ({code})")
+
+
+_lib = None
+_vp, _i64, _u64, _u32, _int, _dbl = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32,
+                                      ctypes.c_int, ctypes.c_double)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_dblp = ctypes.POINTER(ctypes.c_double)
+
+_SIGNATURES = {
+    "sca_state_words": ([_i64, _i64], ctypes.c_size_t),
+    "sca_strerror": ([_int], ctypes.c_char_p),
+    "sca_init": ([ctypes.POINTER(_vp), _i64, _i64, _u64, _vp, _vp, _vp], _int),
+    "sca_step": ([_vp, _i64, _dbl, _dbl], _int),
+    "sca_step_ex": ([_vp, _i64, _dbl, _dbl, ctypes.c_uint], _int),
+    "sca_heights": ([_vp, _i64, _i64, _vp], _int),
+    "sca_roughness": ([_vp, _i64p, _dblp], _int),
+    "sca_snapshot_bytes": ([_vp], ctypes.c_size_t),
+    "sca_snapshot": ([_vp, _vp], _int),
+    "sca_autocorr": ([_vp, _vp, _i64p, _dblp], _int),
+    "sca_get_meta": ([_vp, _i64p, _i64p], _int),
+    "sca_set_time": ([_vp, _i64], _int),
+    "sca_debug_halfstep": ([_vp, _int, _vp, _vp], _int),
+    "sca_debug_philox": ([_vp, _u32, _u32, _i64, _vp, _vp], _int),
+    "sca_destroy": ([_vp], None),
+}
+
+
+def lib():
+    """The loaded library; raises if it was not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1606_00310_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _strerror(code: int) -> str:
+    try:
+        return lib().sca_strerror(code).decode()
+    except Exception:  # pragma: no cover - library not loadable
+        return "status"
+
+
+def check(code: int, what: str):
+    if code != SCA_OK:
+        raise ScaError(code, what)

@@ -1,0 +1,66 @@
+// sca_internal.hpp -- declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sca {
+
+// How the acceptance words of a half-step are produced.
+enum class XiMode : int {
+    Mask = 0,     // dyadic p, q: and/or fold of n 64-bit draws (Sec. III)
+    PerSite = 1,  // one 32-bit uniform per site against floor(r*2^32) (Sec. II-B)
+    Inject = 2,   // read from caller arrays (test hook)
+};
+
+// Everything a half-step launch needs; passed by value as the kernel argument.
+struct SweepArgs {
+    uint64_t* S;       // S[2][2][Y][W]
+    int64_t plane;     // Y*W words per (direction, parity) array
+    int32_t W;         // words per row and sublattice
+    int32_t Y;         // rows
+    int32_t nb;        // used bits per word: 64, or X/2 when X < 128
+    int32_t parity;    // sublattice: 0 even, 1 odd
+    uint32_t t;        // MCS index (Philox counter word 1)
+    uint32_t k0, k1;   // Philox key
+    // Mask mode: bit i-1 of dig_* is binary digit b_i of p or q; ndraw = n;
+    // all_* = ~0 when the probability is exactly 1.
+    uint32_t dig_p, dig_q;
+    int32_t ndraw;
+    uint64_t all_p, all_q;
+    // PerSite mode: thresholds clamped to 32 bits; all_* as above for r == 1.
+    uint32_t thr_p, thr_q;
+    // Inject mode.
+    const uint64_t* xi_p;
+    const uint64_t* xi_q;
+    int64_t* h0;       // origin height h(0,0), updated by the lane owning site (0,0)
+};
+
+// Launches one half-step; returns the launch status.
+hipError_t launch_halfstep(const SweepArgs& a, XiMode mode, bool has_q, hipStream_t stream);
+
+// Flat initial surface into S and h0 = 0.
+hipError_t launch_flat_init(uint64_t* S, int64_t Y, int32_t W, int32_t nb, int64_t* h0,
+                            hipStream_t stream);
+
+// Per-row sums for the moments (and the two-time sums when snap != nullptr):
+// rows[y*3 + {0,1,2}] = {sum_x P_t, sum_x P_t^2 (or sum_x P_t P_s), sum_x P_s}
+// with P(x) = h(x,y) - h(0,y).
+hipError_t launch_row_sums(const uint64_t* S, const uint64_t* snap, int64_t X, int64_t Y,
+                           int32_t W, int32_t nb, int64_t* rows, hipStream_t stream);
+
+// Column prefix h(0,y) and the final exact sums (128-bit) into res[]:
+// res = {S1 lo,hi, S2 lo,hi, S3 lo,hi}; see measure.hip for their meaning.
+hipError_t launch_combine(const uint64_t* S, const int64_t* h0, const uint64_t* snap,
+                          const int64_t* snap_h0, int64_t X, int64_t Y, int32_t W,
+                          const int64_t* rows, int64_t* col, int64_t* res, hipStream_t stream);
+
+// Heights of rows [y0, y0+ny) into out (needs col[] from launch_combine).
+hipError_t launch_heights(const uint64_t* S, int64_t X, int64_t Y, int32_t W, int32_t nb,
+                          const int64_t* col, int64_t y0, int64_t ny, int32_t* out,
+                          hipStream_t stream);
+
+hipError_t launch_philox_test(const uint32_t* ctr, uint32_t k0, uint32_t k1, int64_t n,
+                              uint32_t* out, hipStream_t stream);
+
+}  // namespace sca

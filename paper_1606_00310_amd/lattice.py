@@ -1,0 +1,113 @@
+"""One octahedron-model lattice on the GPU: torch tensors for the device
+memory and stream, every step of the computation in libsca.so."""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib as L
+
+
+class Lattice:
+    """X x Y lattice with periodic boundaries, flat initial surface
+    h(x,y) = (x+y)&1, slopes packed 64 sites per uint64 word in four
+    role-grouped arrays (int64 tensor of shape (2, 2, Y, W), W = max(1, X/128)).
+    """
+
+    def __init__(self, X: int, Y: int, seed: int, device="cuda", stream: torch.cuda.Stream | None = None):
+        self.X, self.Y, self.seed = int(X), int(Y), int(seed)
+        self.device = torch.device(device)
+        n = L.lib().sca_state_words(self.X, self.Y)
+        if n == 0:
+            raise L.ScaError(L.SCA_EINVAL, f"lattice size {X}x{Y}")
+        self.W = max(1, self.X // 128)
+        self.slopes = torch.empty((2, 2, self.Y, self.W), dtype=torch.int64, device=self.device)
+        self.aux = torch.zeros(L.SCA_AUX_LEN, dtype=torch.int64, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ctx = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            L.check(L.lib().sca_init(ctypes.byref(ctx), self.X, self.Y, self.seed, self.slopes.data_ptr(),
+                                     self.aux.data_ptr(), self.stream.cuda_stream), "sca_init")
+        self._ctx = ctx
+
+    # ------------------------------------------------------------------ steps
+    def step(self, n_mcs: int, p: float, q: float = 0.0, force_persite: bool = False):
+        flags = L.SCA_FORCE_PERSITE if force_persite else 0
+        L.check(L.lib().sca_step_ex(self._ctx, int(n_mcs), float(p), float(q), flags), "sca_step")
+        return self
+
+    def debug_halfstep(self, parity: int, xi_p: torch.Tensor, xi_q: torch.Tensor):
+        """Half-step with injected acceptance words (int64 tensors of Y*W words)."""
+        for xi in (xi_p, xi_q):
+            if xi.dtype != torch.int64 or xi.numel() != self.Y * self.W or not xi.is_contiguous() \
+                    or xi.device != self.device:
+                raise ValueError("acceptance words must be contiguous int64 device tensors of Y*W words")
+        L.check(L.lib().sca_debug_halfstep(self._ctx, int(parity), xi_p.data_ptr(), xi_q.data_ptr()),
+                "sca_debug_halfstep")
+
+    # ------------------------------------------------------------ measurement
+    def heights(self, y0: int = 0, ny: int | None = None) -> torch.Tensor:
+        ny = self.Y - y0 if ny is None else ny
+        out = torch.empty((ny, self.X), dtype=torch.int32, device=self.device)
+        L.check(L.lib().sca_heights(self._ctx, int(y0), int(ny), out.data_ptr()), "sca_heights")
+        return out
+
+    def roughness(self):
+        """(N, sum h, sum h^2, W^2)."""
+        out = (ctypes.c_int64 * 3)()
+        w2 = ctypes.c_double()
+        L.check(L.lib().sca_roughness(self._ctx, out, ctypes.byref(w2)), "sca_roughness")
+        return int(out[0]), int(out[1]), int(out[2]), float(w2.value)
+
+    def snapshot(self) -> torch.Tensor:
+        nbytes = L.lib().sca_snapshot_bytes(self._ctx)
+        snap = torch.empty(nbytes // 8, dtype=torch.int64, device=self.device)
+        L.check(L.lib().sca_snapshot(self._ctx, snap.data_ptr()), "sca_snapshot")
+        return snap
+
+    def autocorr(self, snap: torch.Tensor):
+        """(N, sum h_t h_s, sum h_t, sum h_s, C(t,s)) against a snapshot."""
+        if snap.numel() * 8 != L.lib().sca_snapshot_bytes(self._ctx) or snap.device != self.device:
+            raise ValueError("snapshot of another lattice size or device")
+        out = (ctypes.c_int64 * 4)()
+        c = ctypes.c_double()
+        L.check(L.lib().sca_autocorr(self._ctx, snap.data_ptr(), out, ctypes.byref(c)), "sca_autocorr")
+        return int(out[0]), int(out[1]), int(out[2]), int(out[3]), float(c.value)
+
+    def meta(self):
+        """(t, h0)."""
+        t = ctypes.c_int64()
+        h0 = ctypes.c_int64()
+        L.check(L.lib().sca_get_meta(self._ctx, ctypes.byref(t), ctypes.byref(h0)), "sca_get_meta")
+        return int(t.value), int(h0.value)
+
+    @property
+    def t(self) -> int:
+        t = ctypes.c_int64()
+        L.check(L.lib().sca_get_meta(self._ctx, ctypes.byref(t), None), "sca_get_meta")
+        return int(t.value)
+
+    def set_time(self, t: int):
+        L.check(L.lib().sca_set_time(self._ctx, int(t)), "sca_set_time")
+
+    def close(self):
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            L.lib().sca_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def debug_philox(ctr: torch.Tensor, key0: int, key1: int) -> torch.Tensor:
+    """Device Philox4x32-10 of counters ctr (int32/uint32-compatible tensor [n, 4])."""
+    ctr = ctr.contiguous()
+    n = ctr.shape[0]
+    out = torch.empty_like(ctr)
+    L.check(L.lib().sca_debug_philox(ctr.data_ptr(), key0 & 0xFFFFFFFF, key1 & 0xFFFFFFFF, n, out.data_ptr(),
+                                     torch.cuda.current_stream(ctr.device).cuda_stream), "sca_debug_philox")
+    return out
