@@ -73,20 +73,24 @@ def time_path(torch, P, X, Y, p, q, seed, steps, warmup, force_persite=False):
     return ms
 
 
-def cpu_baseline(X, Y, p, q, seed, rows, n_mcs):
-    """The oracle, untuned, on a band of `rows` full-width rows (a light-cone
-    patch with a frozen border) for n_mcs MCS."""
+def cpu_baseline(X, Y, p, q, seed, rows, budget_s, max_mcs=200):
+    """The oracle, untuned, on a band of `rows` full-width rows of the same
+    workload (a light-cone patch with a frozen border), one MCS at a time
+    until about budget_s seconds of CPU work."""
     import oracle
 
     st = oracle.flat_patch(X, Y, 0, 0, X, rows, track_heights=False) if rows < Y else oracle.flat(X, Y, False)
-    t0 = time.perf_counter()
-    oracle.run(st, n_mcs, p, q, seed=seed)
-    dt = time.perf_counter() - t0
+    n, dt = 0, 0.0
+    while dt < budget_s and n < max_mcs:
+        t0 = time.perf_counter()
+        oracle.run(st, 1, p, q, seed=seed)
+        dt += time.perf_counter() - t0
+        n += 1
     sites = X * rows
-    return {"value": sites * n_mcs / dt, "unit": "site updates/s", "cores": oracle.num_threads(),
+    return {"value": sites * n / dt, "unit": "site updates/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": f"{X} x {rows} band of the {X}x{Y} p={p} q={q} workload (frozen border), {n_mcs} MCS, "
-                      f"{dt:.1f} s"}
+            "sample": f"{X} x {rows} band of the {X}x{Y} p={p} q={q} workload (frozen border), {n} MCS "
+                      f"in {dt:.1f} s"}
 
 
 def main():
@@ -97,7 +101,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--no-paths", action="store_true", help="skip the secondary paths")
     ap.add_argument("--cpu-rows", type=int, default=16384)
-    ap.add_argument("--cpu-mcs", type=int, default=6)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 1 GiB device copy (torch copy_) three times, the known-size "
+                         "reference for HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -109,6 +116,15 @@ def main():
     _ensure_built()
     import paper_1606_00310_amd as P
     from paper_1606_00310_amd.inputs import HEADLINE, HEADLINE_RANDOM, PERSITE
+
+    if args.copy_calibration:
+        src = torch.ones(2**30 // 8, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        torch.cuda.empty_cache()
 
     w = HEADLINE
     K, Wm = args.steps, args.warmup
@@ -144,7 +160,7 @@ def main():
         out["paths"] = paths
 
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w.X, w.Y, w.p, w.q, w.seed, args.cpu_rows, args.cpu_mcs)
+        out["cpu_baseline"] = cpu_baseline(w.X, w.Y, w.p, w.q, w.seed, args.cpu_rows, args.cpu_seconds)
 
     print(json.dumps(out), flush=True)
 

@@ -18,6 +18,8 @@ class Lattice:
     def __init__(self, X: int, Y: int, seed: int, device="cuda", stream: torch.cuda.Stream | None = None):
         self.X, self.Y, self.seed = int(X), int(Y), int(seed)
         self.device = torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
         n = L.lib().sca_state_words(self.X, self.Y)
         if n == 0:
             raise L.ScaError(L.SCA_EINVAL, f"lattice size {X}x{Y}")

@@ -181,7 +181,10 @@ def test_exhaustive_4x4_tiled(orc, sca, parity):
     xi = U.pattern_to_words(Lb, Lb, parity, bits)
     xi_dev = torch.from_numpy(xi.view(np.int64)).cuda()
 
-    # expected 4x4 results per (surface, pattern)
+    # expected 4x4 heights per (surface, pattern).  A site's height change
+    # depends only on its own copy (its neighbours' heights repeat with the
+    # tiling), so the tiled result is the per-copy heights; the slope bits on
+    # the bonds between copies then follow from those heights.
     B = len(S) * 256
     sx = np.empty((B, 4, 4), np.uint8)
     sy = np.empty((B, 4, 4), np.uint8)
@@ -189,12 +192,13 @@ def test_exhaustive_4x4_tiled(orc, sca, parity):
         a, b = U.slopes_from_heights(s)
         sx[i * 256:(i + 1) * 256] = a
         sy[i * 256:(i + 1) * 256] = b
+    H4 = np.repeat(S, 256, axis=0).astype(np.int32)
     xi4 = np.zeros((B, 4), np.uint64)
     pp = np.tile(np.arange(256), len(S))
     for y in range(4):
         for k in range(2):
             xi4[:, y] |= (((pp >> (2 * y + k)) & 1).astype(np.uint64)) << np.uint64(k)
-    orc.halfstep_xi_batch(4, 4, sx, sy, None, None, parity, xi4, xi4)
+    orc.halfstep_xi_batch(4, 4, sx, sy, H4, None, parity, xi4, xi4)
 
     lat = sca.Lattice(Lb, Lb, seed=0)
     for i, s in enumerate(S):
@@ -202,11 +206,9 @@ def test_exhaustive_4x4_tiled(orc, sca, parity):
         lat.slopes.copy_(torch.from_numpy(orc.pack(orc.State(Lb, Lb, a, b)).view(np.int64)))
         lat.debug_halfstep(parity, xi_dev, xi_dev)
         got = gpu_state(lat)
-        esx = sx[i * 256 + pat]            # [128,128,4,4]
-        esy = sy[i * 256 + pat]
-        big_x = esx.transpose(0, 2, 1, 3).reshape(Lb, Lb)
-        big_y = esy.transpose(0, 2, 1, 3).reshape(Lb, Lb)
-        ref = orc.pack(orc.State(Lb, Lb, np.ascontiguousarray(big_x), np.ascontiguousarray(big_y)))
+        big_h = H4[i * 256 + pat].transpose(0, 2, 1, 3).reshape(Lb, Lb)   # [128,128,4,4] -> rows, cols
+        ea, eb = U.slopes_from_heights(big_h)
+        ref = orc.pack(orc.State(Lb, Lb, ea, eb))
         assert np.array_equal(got, ref), i
 
 
