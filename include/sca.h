@@ -66,6 +66,7 @@ enum sca_status {
 
 /* sca_step_ex flags */
 #define SCA_FORCE_PERSITE 1u /* use per-site 32-bit compares even for dyadic p, q */
+#define SCA_STEP_GRAPH 2u    /* capture the MCS loop into one hipGraph and launch it once */
 
 /* Length of the caller-owned int64 aux buffer; aux[0] holds h(0,0). */
 #define SCA_AUX_LEN 8
@@ -89,7 +90,10 @@ int sca_init(sca_ctx** out, int64_t X, int64_t Y, uint64_t seed, void* slopes_de
  * (Sec. I-A), t grows by n_mcs.  Asynchronous. */
 int sca_step(sca_ctx* ctx, int64_t n_mcs, double p, double q);
 
-/* sca_step with flags (SCA_FORCE_PERSITE). */
+/* sca_step with flags (SCA_FORCE_PERSITE, SCA_STEP_GRAPH).  With
+ * SCA_STEP_GRAPH the 2*n_mcs half-step launches are captured into a hipGraph
+ * that is launched once (one launch for the whole run) and then released;
+ * this call then synchronizes the stream. */
 int sca_step_ex(sca_ctx* ctx, int64_t n_mcs, double p, double q, unsigned flags);
 
 /* Heights h(x,y) of rows [y0, y0+ny), all x, row-major int32 into out_dev
@@ -140,6 +144,86 @@ int sca_debug_philox(const uint32_t* ctr_dev, uint32_t k0, uint32_t k1, int64_t 
 /* Frees the context and its workspace (after synchronizing its stream).
  * Never frees caller buffers.  NULL is ignored. */
 void sca_destroy(sca_ctx* ctx);
+
+/* ------------------------------------------------------------------------ */
+/* Ensembles: many independent realizations in one persistent launch.       */
+/* ------------------------------------------------------------------------ */
+/* A batch advances thousands of independent lattices of uneven size in one
+ * persistent, hipGraph-captured kernel launch per epoch.  Each realization
+ * draws from its own seed with the same counters as the single-lattice path,
+ * so its state after any number of MCS is bit-identical to a solo run of the
+ * same (X, Y, p, q, seed) -- independent of the schedule and configuration.
+ * States live in a caller-owned device arena; the library keeps a small
+ * table of per-slot descriptors on the device. */
+
+typedef struct sca_batch sca_batch;
+
+/* One realization: X, Y powers of two with 4 <= X <= 8192, 4 <= Y <= 131072;
+ * 0 <= p, q <= 1; n_mcs >= 0 MCS in total; flags: SCA_FORCE_PERSITE. */
+typedef struct sca_req {
+    int64_t X, Y;
+    double p, q;
+    int64_t n_mcs;
+    uint64_t seed;
+    uint32_t flags;
+    uint32_t reserved; /* must be 0 */
+} sca_req;
+
+/* Launch shape and schedule of the persistent kernel.  Every setting gives
+ * bit-identical results; only the speed differs. */
+typedef struct sca_batch_config {
+    int32_t block_threads; /* workgroup size: 256, 512 or 1024 */
+    int32_t blocks_per_cu; /* persistent workgroups per compute unit, 1..8 */
+    int32_t lds_bytes;     /* realizations with 32*X*Y/128 <= lds_bytes bytes of
+                              state (X >= 128; 4*Y*8 bytes for X < 128) run
+                              from LDS; 0 = never; at most 65536 */
+    int32_t order;         /* 0: longest remaining work first, 1: slot order */
+} sca_batch_config;
+
+typedef struct sca_slot_info {
+    int64_t X, Y, t, n_mcs;
+    uint64_t seed;
+    void* slopes_dev;      /* the realization's S[2][2][Y][W] inside the arena */
+    int64_t* h0_dev;       /* its h(0,0) inside the arena */
+} sca_slot_info;
+
+/* Arena bytes one realization of size X x Y occupies (256-byte aligned). */
+size_t sca_batch_state_bytes(int64_t X, int64_t Y);
+
+/* Creates a batch with room for max_slots realizations whose states are
+ * placed in the caller-owned device arena [arena_dev, arena_dev+arena_bytes)
+ * (the HBM budget).  Work is enqueued on hip_stream.  The library allocates
+ * the descriptor table (about 160 bytes per slot) and pinned staging. */
+int sca_batch_create(sca_batch** out, int32_t max_slots, void* arena_dev, size_t arena_bytes,
+                     void* hip_stream);
+
+int sca_batch_set_config(sca_batch* b, const sca_batch_config* cfg);
+int sca_batch_get_config(const sca_batch* b, sca_batch_config* cfg);
+
+/* Admits n realizations, all or none: SCA_EBUSY if the free slots or the free
+ * arena space do not suffice (nothing is changed then).  Each admitted
+ * realization starts from the flat surface at t = 0; slots_out[i] receives
+ * its slot.  Asynchronous (the flat initialisation is enqueued). */
+int sca_batch_admit(sca_batch* b, const sca_req* reqs, int32_t n, int32_t* slots_out);
+
+/* One epoch: every admitted realization with work left advances
+ * min(mcs_epoch, n_mcs - t) MCS, all in one persistent launch.  *active_out
+ * (optional) receives the number of realizations that ran.  Asynchronous. */
+int sca_batch_run(sca_batch* b, int64_t mcs_epoch, int32_t* active_out);
+
+/* Slot description; SCA_EINVAL for a free slot.  t is the MCS count the slot
+ * will have reached once the enqueued epochs have run. */
+int sca_batch_slot(const sca_batch* b, int32_t slot, sca_slot_info* out);
+
+/* Exact moments {N, sum h, sum h^2} and W^2 of one slot's current state
+ * (as sca_roughness).  Synchronizes. */
+int sca_batch_roughness(sca_batch* b, int32_t slot, int64_t out3[3], double* w2);
+
+/* Frees a slot and its arena space (after the enqueued work that uses it). */
+int sca_batch_release(sca_batch* b, int32_t slot);
+
+/* Frees the batch (after synchronizing its stream); never frees the arena. */
+void sca_batch_destroy(sca_batch* b);
 
 /* Static description of a status code. */
 const char* sca_strerror(int code);

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libsca.so")
 
 SCA_OK, SCA_EINVAL, SCA_ENOMEM, SCA_EDEVICE, SCA_EOVERFLOW, SCA_ESTATE, SCA_EBUSY = 0, -1, -2, -3, -4, -5, -6
 SCA_FORCE_PERSITE = 1
+SCA_STEP_GRAPH = 2
 SCA_AUX_LEN = 8
 
 
@@ -22,6 +23,27 @@ class ScaError(RuntimeError):
     def __init__(self, code: int, what: str):
         self.code = code
         super().__init__(f"{what}: {_strerror(code)} ({code})")
+
+
+class Req(ctypes.Structure):
+    """sca_req: one realization of an ensemble."""
+    _fields_ = [("X", ctypes.c_int64), ("Y", ctypes.c_int64), ("p", ctypes.c_double), ("q", ctypes.c_double),
+                ("n_mcs", ctypes.c_int64), ("seed", ctypes.c_uint64), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class BatchConfig(ctypes.Structure):
+    """sca_batch_config: launch shape and schedule of the persistent kernel."""
+    _fields_ = [("block_threads", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("lds_bytes", ctypes.c_int32), ("order", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+class SlotInfo(ctypes.Structure):
+    _fields_ = [("X", ctypes.c_int64), ("Y", ctypes.c_int64), ("t", ctypes.c_int64), ("n_mcs", ctypes.c_int64),
+                ("seed", ctypes.c_uint64), ("slopes_dev", ctypes.c_void_p), ("h0_dev", ctypes.c_void_p)]
 
 
 _lib = None
@@ -46,6 +68,16 @@ _SIGNATURES = {
     "sca_debug_halfstep": ([_vp, _int, _vp, _vp], _int),
     "sca_debug_philox": ([_vp, _u32, _u32, _i64, _vp, _vp], _int),
     "sca_destroy": ([_vp], None),
+    "sca_batch_state_bytes": ([_i64, _i64], ctypes.c_size_t),
+    "sca_batch_create": ([ctypes.POINTER(_vp), ctypes.c_int32, _vp, ctypes.c_size_t, _vp], _int),
+    "sca_batch_set_config": ([_vp, ctypes.POINTER(BatchConfig)], _int),
+    "sca_batch_get_config": ([_vp, ctypes.POINTER(BatchConfig)], _int),
+    "sca_batch_admit": ([_vp, ctypes.POINTER(Req), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)], _int),
+    "sca_batch_run": ([_vp, _i64, ctypes.POINTER(ctypes.c_int32)], _int),
+    "sca_batch_slot": ([_vp, ctypes.c_int32, ctypes.POINTER(SlotInfo)], _int),
+    "sca_batch_roughness": ([_vp, ctypes.c_int32, _i64p, _dblp], _int),
+    "sca_batch_release": ([_vp, ctypes.c_int32], _int),
+    "sca_batch_destroy": ([_vp], None),
 }
 
 

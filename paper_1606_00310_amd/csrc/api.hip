@@ -11,7 +11,10 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
+#include <map>
 #include <new>
+#include <vector>
 
 #include "sca.h"
 #include "sca_internal.hpp"
@@ -27,6 +30,7 @@ struct sca_ctx {
     int64_t t = 0;
     bool failed = false;
     int64_t* ws = nullptr;     // library-owned: rows[3Y], col[Y], res[8]
+    hipStream_t capture = nullptr;  // private stream for hipGraph capture (created on first use)
 };
 
 namespace {
@@ -106,6 +110,55 @@ __int128 join128(int64_t lo, int64_t hi) { return (__int128)(((unsigned __int128
 
 bool fits64(__int128 v) { return v >= (__int128)INT64_MIN && v <= (__int128)INT64_MAX; }
 
+// Exact moments of a state at S with origin height *h0, using ws (rows[3Y],
+// col[Y], res[8]).  Returns SCA_OK, SCA_EDEVICE or SCA_EOVERFLOW.
+int moments_of(const uint64_t* S, const int64_t* h0, int64_t X, int64_t Y, int32_t W, int32_t nb, int64_t* ws,
+               hipStream_t stream, int64_t out3[3], double* w2)
+{
+    int64_t* rows = ws;
+    int64_t* col = ws + 3 * Y;
+    int64_t* res = ws + 4 * Y;
+    if (sca::launch_row_sums(S, nullptr, X, Y, W, nb, rows, stream) != hipSuccess) return SCA_EDEVICE;
+    if (sca::launch_combine(S, h0, nullptr, nullptr, X, Y, W, rows, col, res, stream) != hipSuccess)
+        return SCA_EDEVICE;
+    int64_t r[6];
+    if (hipMemcpyAsync(r, res, sizeof r, hipMemcpyDeviceToHost, stream) != hipSuccess) return SCA_EDEVICE;
+    if (hipStreamSynchronize(stream) != hipSuccess) return SCA_EDEVICE;
+    const __int128 s1 = join128(r[0], r[1]), s2 = join128(r[2], r[3]);
+    if (!fits64(s1) || !fits64(s2)) return SCA_EOVERFLOW;
+    const __int128 N = (__int128)X * Y;
+    out3[0] = (int64_t)N;
+    out3[1] = (int64_t)s1;
+    out3[2] = (int64_t)s2;
+    if (w2) *w2 = (double)(N * s2 - s1 * s1) / ((double)N * (double)N);
+    return SCA_OK;
+}
+
+// Runs `enqueue` on a private capture stream into a hipGraph, then launches
+// the instantiated graph once on `stream`.  The launch is synchronized before
+// the graph is released.
+template <typename F>
+hipError_t run_as_graph(hipStream_t& capture, hipStream_t stream, F enqueue)
+{
+    if (!capture && hipStreamCreateWithFlags(&capture, hipStreamNonBlocking) != hipSuccess) return hipErrorUnknown;
+    if (hipStreamBeginCapture(capture, hipStreamCaptureModeRelaxed) != hipSuccess) return hipErrorUnknown;
+    const hipError_t e1 = enqueue(capture);
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(capture, &graph);
+    if (e1 != hipSuccess || e2 != hipSuccess || !graph) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : hipErrorUnknown);
+    }
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return e;
+    e = hipGraphLaunch(exec, stream);
+    const hipError_t es = hipStreamSynchronize(stream);
+    (void)hipGraphExecDestroy(exec);
+    return e != hipSuccess ? e : es;
+}
+
 }  // namespace
 
 extern "C" {
@@ -164,7 +217,8 @@ int sca_step_ex(sca_ctx* c, int64_t n_mcs, double p, double q, unsigned flags)
 {
     if (!c) return SCA_EINVAL;
     if (c->failed) return SCA_ESTATE;
-    if (n_mcs < 0 || !valid_prob(p) || !valid_prob(q) || (flags & ~SCA_FORCE_PERSITE)) return SCA_EINVAL;
+    if (n_mcs < 0 || !valid_prob(p) || !valid_prob(q) || (flags & ~(SCA_FORCE_PERSITE | SCA_STEP_GRAPH)))
+        return SCA_EINVAL;
     if (c->t + n_mcs > (int64_t)UINT32_MAX) return SCA_EINVAL;
     if (n_mcs == 0) return SCA_OK;
     DeviceGuard dg(c->device);
@@ -193,13 +247,20 @@ int sca_step_ex(sca_ctx* c, int64_t n_mcs, double p, double q, unsigned flags)
         a.ndraw = P.n > Q.n ? P.n : Q.n;
     }
     const sca::XiMode mode = persite ? sca::XiMode::PerSite : sca::XiMode::Mask;
-    for (int64_t i = 0; i < n_mcs; ++i) {
-        a.t = (uint32_t)(c->t + i);
-        for (int parity = 0; parity < 2; ++parity) {
-            a.parity = parity;
-            if (sca::launch_halfstep(a, mode, has_q, c->stream) != hipSuccess) return fail(c);
+    const int64_t t0 = c->t;
+    auto enqueue = [&](hipStream_t st) -> hipError_t {
+        for (int64_t i = 0; i < n_mcs; ++i) {
+            a.t = (uint32_t)(t0 + i);
+            for (int parity = 0; parity < 2; ++parity) {
+                a.parity = parity;
+                const hipError_t e = sca::launch_halfstep(a, mode, has_q, st);
+                if (e != hipSuccess) return e;
+            }
         }
-    }
+        return hipSuccess;
+    };
+    const hipError_t e = (flags & SCA_STEP_GRAPH) ? run_as_graph(c->capture, c->stream, enqueue) : enqueue(c->stream);
+    if (e != hipSuccess) return fail(c);
     c->t += n_mcs;
     return SCA_OK;
 }
@@ -243,22 +304,9 @@ int sca_roughness(sca_ctx* c, int64_t out3[3], double* w2)
     if (c->failed) return SCA_ESTATE;
     DeviceGuard dg(c->device);
     if (!dg.ok) return fail(c);
-    if (sca::launch_row_sums(c->S, nullptr, c->X, c->Y, c->W, c->nb, ws_rows(c), c->stream) != hipSuccess)
-        return fail(c);
-    if (sca::launch_combine(c->S, c->aux, nullptr, nullptr, c->X, c->Y, c->W, ws_rows(c), ws_col(c), ws_res(c),
-                            c->stream) != hipSuccess)
-        return fail(c);
-    int64_t r[6];
-    const int rc = read_back(c, ws_res(c), r, 6);
-    if (rc != SCA_OK) return rc;
-    const __int128 s1 = join128(r[0], r[1]), s2 = join128(r[2], r[3]);
-    if (!fits64(s1) || !fits64(s2)) return SCA_EOVERFLOW;
-    const __int128 N = (__int128)c->X * c->Y;
-    out3[0] = (int64_t)N;
-    out3[1] = (int64_t)s1;
-    out3[2] = (int64_t)s2;
-    if (w2) *w2 = (double)(N * s2 - s1 * s1) / ((double)N * (double)N);
-    return SCA_OK;
+    const int rc = moments_of(c->S, c->aux, c->X, c->Y, c->W, c->nb, c->ws, c->stream, out3, w2);
+    if (rc == SCA_EDEVICE) return fail(c);
+    return rc;
 }
 
 size_t sca_snapshot_bytes(const sca_ctx* c)
@@ -358,8 +406,408 @@ void sca_destroy(sca_ctx* c)
         DeviceGuard dg(c->device);
         (void)hipStreamSynchronize(c->stream);
         (void)hipFree(c->ws);
+        if (c->capture) (void)hipStreamDestroy(c->capture);
     }
     delete c;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Ensembles
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kArenaAlign = 256;
+
+size_t state_bytes(int64_t X, int64_t Y)
+{
+    const size_t words = (size_t)(4 * Y * (X >= 128 ? X / 128 : 1)) + 1;  // + h(0,0)
+    return (words * sizeof(uint64_t) + kArenaAlign - 1) / kArenaAlign * kArenaAlign;
+}
+
+// First-fit allocator over [0, size) with coalescing of freed ranges.
+class ArenaAllocator {
+public:
+    void reset(size_t size)
+    {
+        free_.clear();
+        if (size) free_[0] = size;
+    }
+    bool alloc(size_t bytes, size_t* off)
+    {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const size_t rest = it->second - bytes;
+                const size_t start = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[start] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes)
+    {
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t free_bytes() const
+    {
+        size_t s = 0;
+        for (const auto& kv : free_) s += kv.second;
+        return s;
+    }
+
+private:
+    std::map<size_t, size_t> free_;  // offset -> length
+};
+
+struct SlotHost {
+    bool used = false;
+    sca_req req{};
+    size_t offset = 0, bytes = 0;
+    int64_t t = 0;          // MCS reached once the enqueued epochs have run
+    int32_t W = 0, nb = 0;
+    sca::BatchDesc desc{};  // static part; t and n_run are set per epoch
+};
+
+bool valid_req(const sca_req& r)
+{
+    return valid_size(r.X, r.Y) && r.X <= 8192 && valid_prob(r.p) && valid_prob(r.q) && r.n_mcs >= 0 &&
+           r.n_mcs <= (int64_t)UINT32_MAX && (r.flags & ~SCA_FORCE_PERSITE) == 0 && r.reserved == 0;
+}
+
+bool valid_cfg(const sca_batch_config& c)
+{
+    return (c.block_threads == 256 || c.block_threads == 512 || c.block_threads == 1024) && c.blocks_per_cu >= 1 &&
+           c.blocks_per_cu <= 8 && c.lds_bytes >= 0 && c.lds_bytes <= 65536 && (c.lds_bytes % 8) == 0 &&
+           (c.order == 0 || c.order == 1);
+}
+
+}  // namespace
+
+struct sca_batch {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t capture = nullptr;
+    uint8_t* arena = nullptr;
+    size_t arena_bytes = 0;
+    int32_t max_slots = 0;
+    int num_cus = 0;
+    std::vector<SlotHost> slots;
+    std::vector<int32_t> free_slots;  // stack of free slot ids
+    ArenaAllocator alloc;
+    sca_batch_config cfg{512, 2, 65536, 0};
+    // device (library-owned)
+    sca::BatchDesc* d_desc = nullptr;
+    int32_t* d_order = nullptr;
+    int32_t* d_counters = nullptr;  // [0] item count, [1] work queue
+    int64_t* d_ws = nullptr;        // moments workspace for Y up to 131072
+    // pinned staging
+    sca::BatchDesc* h_desc = nullptr;
+    int32_t* h_order = nullptr;
+    int32_t* h_count = nullptr;
+    hipEvent_t staged = nullptr;
+    bool staged_pending = false;
+    hipGraphExec_t exec = nullptr;
+    bool failed = false;
+};
+
+namespace {
+
+int bfail(sca_batch* b)
+{
+    if (b) b->failed = true;
+    return SCA_EDEVICE;
+}
+
+void batch_free(sca_batch* b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->staged) (void)hipEventDestroy(b->staged);
+    if (b->capture) (void)hipStreamDestroy(b->capture);
+    (void)hipFree(b->d_desc);
+    (void)hipFree(b->d_order);
+    (void)hipFree(b->d_counters);
+    (void)hipFree(b->d_ws);
+    (void)hipHostFree(b->h_desc);
+    (void)hipHostFree(b->h_order);
+    (void)hipHostFree(b->h_count);
+    delete b;
+}
+
+// (Re)captures the epoch graph: reset the work counter, then the persistent
+// kernel.  The table, order and count are read from device memory, so the
+// graph is reused for every epoch until the configuration changes.
+hipError_t capture_epoch_graph(sca_batch* b)
+{
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    if (!b->capture && hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess)
+        return hipErrorUnknown;
+    sca::BatchLaunch L{b->d_desc, b->d_order, b->d_counters, b->d_counters + 1, b->cfg.lds_bytes};
+    if (hipStreamBeginCapture(b->capture, hipStreamCaptureModeRelaxed) != hipSuccess) return hipErrorUnknown;
+    hipError_t e1 = sca::launch_counter_reset(b->d_counters + 1, b->capture);
+    if (e1 == hipSuccess) e1 = sca::launch_ensemble(L, b->cfg.block_threads, b->num_cus * b->cfg.blocks_per_cu, b->capture);
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(b->capture, &graph);
+    if (e1 != hipSuccess || e2 != hipSuccess || !graph) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : hipErrorUnknown);
+    }
+    const hipError_t e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sca_batch_state_bytes(int64_t X, int64_t Y)
+{
+    if (!valid_size(X, Y)) return 0;
+    return state_bytes(X, Y);
+}
+
+int sca_batch_create(sca_batch** out, int32_t max_slots, void* arena_dev, size_t arena_bytes, void* hip_stream)
+{
+    if (!out || max_slots <= 0 || max_slots > (1 << 20) || (!arena_dev && arena_bytes)) return SCA_EINVAL;
+    *out = nullptr;
+    sca_batch* b = new (std::nothrow) sca_batch;
+    if (!b) return SCA_ENOMEM;
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    b->arena = static_cast<uint8_t*>(arena_dev);
+    b->arena_bytes = arena_bytes;
+    b->max_slots = max_slots;
+    try {
+        b->slots.resize((size_t)max_slots);
+        b->free_slots.reserve((size_t)max_slots);
+    } catch (...) {
+        delete b;
+        return SCA_ENOMEM;
+    }
+    for (int32_t s = max_slots - 1; s >= 0; --s) b->free_slots.push_back(s);
+    b->alloc.reset(arena_bytes);
+    if (hipGetDevice(&b->device) != hipSuccess ||
+        hipDeviceGetAttribute(&b->num_cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess) {
+        delete b;
+        return SCA_EDEVICE;
+    }
+    const size_t nd = sizeof(sca::BatchDesc) * (size_t)max_slots, no = sizeof(int32_t) * (size_t)max_slots;
+    if (hipMalloc(&b->d_desc, nd) != hipSuccess || hipMalloc(&b->d_order, no) != hipSuccess ||
+        hipMalloc(&b->d_counters, 2 * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&b->d_ws, sizeof(int64_t) * (size_t)(4 * 131072 + 8)) != hipSuccess ||
+        hipHostMalloc(&b->h_desc, nd, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&b->h_order, no, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&b->h_count, sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        batch_free(b);
+        return SCA_ENOMEM;
+    }
+    std::memset(b->h_desc, 0, nd);
+    *out = b;
+    return SCA_OK;
+}
+
+int sca_batch_set_config(sca_batch* b, const sca_batch_config* cfg)
+{
+    if (!b || !cfg || !valid_cfg(*cfg)) return SCA_EINVAL;
+    if (b->failed) return SCA_ESTATE;
+    const bool same = cfg->block_threads == b->cfg.block_threads && cfg->blocks_per_cu == b->cfg.blocks_per_cu &&
+                      cfg->lds_bytes == b->cfg.lds_bytes && cfg->order == b->cfg.order;
+    if (same) return SCA_OK;
+    DeviceGuard dg(b->device);
+    if (!dg.ok) return bfail(b);
+    // the old graph may still be in flight on the stream
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return bfail(b);
+    b->cfg = *cfg;
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    return SCA_OK;
+}
+
+int sca_batch_get_config(const sca_batch* b, sca_batch_config* cfg)
+{
+    if (!b || !cfg) return SCA_EINVAL;
+    *cfg = b->cfg;
+    return SCA_OK;
+}
+
+int sca_batch_admit(sca_batch* b, const sca_req* reqs, int32_t n, int32_t* slots_out)
+{
+    if (!b || n < 0 || (n > 0 && (!reqs || !slots_out))) return SCA_EINVAL;
+    if (b->failed) return SCA_ESTATE;
+    for (int32_t i = 0; i < n; ++i)
+        if (!valid_req(reqs[i])) return SCA_EINVAL;
+    if ((size_t)n > b->free_slots.size()) return SCA_EBUSY;
+    // all or nothing: place every state first
+    std::vector<size_t> offs((size_t)n);
+    int32_t placed = 0;
+    for (; placed < n; ++placed) {
+        if (!b->alloc.alloc(state_bytes(reqs[placed].X, reqs[placed].Y), &offs[(size_t)placed])) break;
+    }
+    if (placed < n) {
+        for (int32_t i = 0; i < placed; ++i)
+            b->alloc.release(offs[(size_t)i], state_bytes(reqs[i].X, reqs[i].Y));
+        return SCA_EBUSY;
+    }
+    DeviceGuard dg(b->device);
+    if (!dg.ok) return bfail(b);
+    for (int32_t i = 0; i < n; ++i) {
+        const sca_req& r = reqs[i];
+        const int32_t slot = b->free_slots.back();
+        b->free_slots.pop_back();
+        SlotHost& s = b->slots[(size_t)slot];
+        s.used = true;
+        s.req = r;
+        s.offset = offs[(size_t)i];
+        s.bytes = state_bytes(r.X, r.Y);
+        s.t = 0;
+        s.W = (int32_t)(r.X >= 128 ? r.X / 128 : 1);
+        s.nb = (int32_t)(r.X >= 128 ? 64 : r.X / 2);
+        const ProbCode P = classify(r.p), Q = classify(r.q);
+        const bool persite = (r.flags & SCA_FORCE_PERSITE) || !P.dyadic || !Q.dyadic;
+        sca::BatchDesc& d = s.desc;
+        d = sca::BatchDesc{};
+        d.S = reinterpret_cast<uint64_t*>(b->arena + s.offset);
+        d.plane = r.Y * s.W;
+        d.h0 = reinterpret_cast<int64_t*>(d.S + 4 * d.plane);
+        d.W = s.W;
+        d.Y = (int32_t)r.Y;
+        d.nb = s.nb;
+        d.mode = persite ? 1 : 0;
+        d.k0 = (uint32_t)r.seed;
+        d.k1 = (uint32_t)(r.seed >> 32);
+        d.all_p = P.all;
+        d.all_q = Q.all;
+        d.has_q = r.q > 0.0 ? 1 : 0;
+        if (persite) {
+            d.thr_p = P.thr;
+            d.thr_q = Q.thr;
+        } else {
+            d.dig_p = P.digits;
+            d.dig_q = Q.digits;
+            d.ndraw = P.n > Q.n ? P.n : Q.n;
+        }
+        if (sca::launch_flat_init(d.S, r.Y, s.W, s.nb, d.h0, b->stream) != hipSuccess) return bfail(b);
+        slots_out[i] = slot;
+    }
+    return SCA_OK;
+}
+
+int sca_batch_run(sca_batch* b, int64_t mcs_epoch, int32_t* active_out)
+{
+    if (!b || mcs_epoch < 0) return SCA_EINVAL;
+    if (b->failed) return SCA_ESTATE;
+    DeviceGuard dg(b->device);
+    if (!dg.ok) return bfail(b);
+    // the staging buffers are free once the previous epoch's copies have run
+    if (b->staged_pending && hipEventSynchronize(b->staged) != hipSuccess) return bfail(b);
+    b->staged_pending = false;
+    int32_t count = 0, hi = -1;
+    std::vector<std::pair<int64_t, int32_t>> work;
+    for (int32_t slot = 0; slot < b->max_slots; ++slot) {
+        SlotHost& s = b->slots[(size_t)slot];
+        if (!s.used) continue;
+        const int64_t left = s.req.n_mcs - s.t;
+        const int64_t run = left < mcs_epoch ? left : mcs_epoch;
+        sca::BatchDesc d = s.desc;
+        d.t = (uint32_t)s.t;
+        d.n_run = (uint32_t)(run > 0 ? run : 0);
+        b->h_desc[slot] = d;
+        hi = slot;
+        if (run > 0) work.emplace_back(run * s.req.X * s.req.Y, slot);
+    }
+    if (b->cfg.order == 0)
+        std::stable_sort(work.begin(), work.end(),
+                         [](const std::pair<int64_t, int32_t>& x, const std::pair<int64_t, int32_t>& y) {
+                             return x.first > y.first;
+                         });
+    for (const auto& w : work) b->h_order[count++] = w.second;
+    if (active_out) *active_out = count;
+    if (count == 0) return SCA_OK;
+    *b->h_count = count;
+    if (hipMemcpyAsync(b->d_desc, b->h_desc, sizeof(sca::BatchDesc) * (size_t)(hi + 1), hipMemcpyHostToDevice,
+                       b->stream) != hipSuccess ||
+        hipMemcpyAsync(b->d_order, b->h_order, sizeof(int32_t) * (size_t)count, hipMemcpyHostToDevice, b->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(b->d_counters, b->h_count, sizeof(int32_t), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+        hipEventRecord(b->staged, b->stream) != hipSuccess)
+        return bfail(b);
+    b->staged_pending = true;
+    if (!b->exec && capture_epoch_graph(b) != hipSuccess) return bfail(b);
+    if (hipGraphLaunch(b->exec, b->stream) != hipSuccess) return bfail(b);
+    for (const auto& w : work) {
+        SlotHost& s = b->slots[(size_t)w.second];
+        const int64_t left = s.req.n_mcs - s.t;
+        s.t += left < mcs_epoch ? left : mcs_epoch;
+    }
+    return SCA_OK;
+}
+
+int sca_batch_slot(const sca_batch* b, int32_t slot, sca_slot_info* out)
+{
+    if (!b || !out || slot < 0 || slot >= b->max_slots || !b->slots[(size_t)slot].used) return SCA_EINVAL;
+    const SlotHost& s = b->slots[(size_t)slot];
+    out->X = s.req.X;
+    out->Y = s.req.Y;
+    out->t = s.t;
+    out->n_mcs = s.req.n_mcs;
+    out->seed = s.req.seed;
+    out->slopes_dev = s.desc.S;
+    out->h0_dev = s.desc.h0;
+    return SCA_OK;
+}
+
+int sca_batch_roughness(sca_batch* b, int32_t slot, int64_t out3[3], double* w2)
+{
+    if (!b || !out3 || slot < 0 || slot >= b->max_slots || !b->slots[(size_t)slot].used) return SCA_EINVAL;
+    if (b->failed) return SCA_ESTATE;
+    DeviceGuard dg(b->device);
+    if (!dg.ok) return bfail(b);
+    const SlotHost& s = b->slots[(size_t)slot];
+    const int rc = moments_of(s.desc.S, s.desc.h0, s.req.X, s.req.Y, s.W, s.nb, b->d_ws, b->stream, out3, w2);
+    if (rc == SCA_EDEVICE) return bfail(b);
+    return rc;
+}
+
+int sca_batch_release(sca_batch* b, int32_t slot)
+{
+    if (!b || slot < 0 || slot >= b->max_slots || !b->slots[(size_t)slot].used) return SCA_EINVAL;
+    SlotHost& s = b->slots[(size_t)slot];
+    b->alloc.release(s.offset, s.bytes);
+    s = SlotHost{};
+    b->free_slots.push_back(slot);
+    return SCA_OK;
+}
+
+void sca_batch_destroy(sca_batch* b)
+{
+    if (!b) return;
+    {
+        DeviceGuard dg(b->device);
+        (void)hipStreamSynchronize(b->stream);
+        batch_free(b);
+    }
 }
 
 }  // extern "C"

@@ -60,6 +60,37 @@ hipError_t launch_heights(const uint64_t* S, int64_t X, int64_t Y, int32_t W, in
                           const int64_t* col, int64_t y0, int64_t ny, int32_t* out,
                           hipStream_t stream);
 
+// One realization of an ensemble epoch (device table, one entry per slot).
+struct BatchDesc {
+    uint64_t* S;       // state S[2][2][Y][W] in the arena
+    int64_t* h0;       // origin height in the arena
+    int64_t plane;     // Y*W
+    int32_t W, Y, nb;
+    int32_t mode;      // 0 mask, 1 per-site
+    uint32_t k0, k1;
+    uint32_t dig_p, dig_q;
+    int32_t ndraw;
+    int32_t has_q;
+    uint32_t thr_p, thr_q;
+    uint64_t all_p, all_q;
+    uint32_t t;        // MCS index at the start of the epoch
+    uint32_t n_run;    // MCS to advance in this epoch (0: skip)
+};
+
+// Arguments of the persistent ensemble kernel; the table, the order and the
+// item count live in device memory so that one captured graph serves every
+// epoch.
+struct BatchLaunch {
+    const BatchDesc* desc;
+    const int32_t* order;    // slots in processing order
+    const int32_t* n_items;  // number of entries of order to process
+    int32_t* queue;          // work counter, reset to 0 before each launch
+    int32_t lds_bytes;       // dynamic LDS per workgroup; states up to this size run from LDS
+};
+
+hipError_t launch_ensemble(const BatchLaunch& L, int block_threads, int grid, hipStream_t stream);
+hipError_t launch_counter_reset(int32_t* counter, hipStream_t stream);
+
 hipError_t launch_philox_test(const uint32_t* ctr, uint32_t k0, uint32_t k1, int64_t n,
                               uint32_t* out, hipStream_t stream);
 

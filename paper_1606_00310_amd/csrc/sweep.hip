@@ -1,212 +1,28 @@
-// sweep.hip -- the bit-vectorized half-step of the octahedron-model SCA on gfx950.
+// sweep.hip -- the single-lattice half-step launch on gfx950.
 //
-// One half-step updates every site of one checkerboard sublattice (Sec. I-A).
-// Sites of the same sublattice share no bond, so the whole sublattice is
-// updated at once with bitwise operations on 64 sites per word (Sec. II-B,
-// Fig. 3; the mask of Eqs. (3)-(5)):
-//
-//   m_p = xi_p & ~x- & ~y- &  x+ &  y+        (local minima, accepted w.p. p)
-//   m_q = xi_q &  x- &  y- & ~x+ & ~y+        (local maxima, accepted w.p. q)
-//   m   = m_p | m_q                           (disjoint, so xor == or)
-//
-// and m is xored into the four slope words of the updated sites.
-//
-// gfx950 mapping.  One wavefront (64 lanes) owns whole rows: a row of W words
-// is spread over a group of G = min(W, 64) lanes holding I = W/G words each
-// (word w = i*G + lane), so each load instruction of the wave moves 512
-// contiguous bytes and every byte of the state is read once and written once
-// per half-step.  The only cross-word traffic -- bit 0 of the next x+ word
-// when the row's x+ neighbours are shifted by one site, and the top bit of
-// the previous word's mask on the way back -- stays inside the wave: one
-// 32-bit ds_bpermute per direction carries that bit for all I slots of a
-// lane.  Because a row never leaves its wave there are no barriers, no LDS
-// buffers and no atomics (the paper needs a block-wide shared buffer and
-// synchronisation for the same rotation, Fig. 3), and the periodic wrap of
-// the row (the paper caches the first word separately, Sec. II-B) is just the
-// rotation of those packed bits.  For W == 1 (X <= 128) a lane owns a whole
-// row and rotates within the X/2 used bits.
-//
-// Row parity: the x+ neighbour of the site in bit k of row y is the site in
-// bit k of the other sublattice's x-array when the row's sites of this parity
-// have even x, and in bit k+1 when they have odd x, i.e. when
-// parity ^ (y & 1) == 1 (the paper's aligned / shifted rows, Sec. II-B).
-#include "philox.hpp"
-#include "sca_internal.hpp"
+// One wavefront owns whole rows: a row of W words is spread over a group of
+// G = min(W, 64) lanes holding I = W/G words each (word w = i*G + lane), so
+// each load instruction of the wave moves 512 contiguous bytes and every byte
+// of the state is read once and written once per half-step.  Because a row
+// never leaves its wave there are no barriers, no LDS buffers and no atomics
+// (the paper needs a block-wide shared buffer and synchronisation for the
+// same rotation, Fig. 3), and the periodic wrap of the row (the paper caches
+// the first word separately, Sec. II-B) is a rotation of packed bits inside
+// the wave.  The arithmetic of a row group lives in halfstep.hpp.
+#include "halfstep.hpp"
 
 namespace sca {
 namespace {
 
 constexpr int kBlock = 256;
 
-// Acceptance words for canonical word g, mask mode: the and/or fold of
-// n = ndraw draws, least significant binary digit first, generated from the
-// last Philox call backwards so that only one call's output is live.
-__device__ __forceinline__ void mask_words(const SweepArgs& a, uint32_t g, bool has_q,
-                                           uint64_t& xp, uint64_t& xq)
-{
-    uint64_t ap = 0, aq = 0;
-    const int ncall = (a.ndraw + 1) >> 1;
-    for (int j = ncall - 1; j >= 0; --j) {
-        const u32x4 o = philox4x32_10(g, a.t, 2u * (uint32_t)j + (uint32_t)a.parity, 0u, a.k0, a.k1);
-        const uint64_t r0 = (uint64_t)o.v0 | ((uint64_t)o.v1 << 32);  // draw 2j
-        const uint64_t r1 = (uint64_t)o.v2 | ((uint64_t)o.v3 << 32);  // draw 2j+1
-        const int d1 = 2 * j + 1;                                     // digit b_{2j+2}
-        if (d1 < a.ndraw) {
-            ap = ((a.dig_p >> d1) & 1u) ? (r1 | ap) : (r1 & ap);
-            if (has_q) aq = ((a.dig_q >> d1) & 1u) ? (r1 | aq) : (r1 & aq);
-        }
-        const int d0 = 2 * j;                                         // digit b_{2j+1}
-        ap = ((a.dig_p >> d0) & 1u) ? (r0 | ap) : (r0 & ap);
-        if (has_q) aq = ((a.dig_q >> d0) & 1u) ? (r0 | aq) : (r0 & aq);
-    }
-    xp = ap | a.all_p;
-    xq = has_q ? (aq | a.all_q) : 0;
-}
-
-// Acceptance words, per-site mode: site bit b compares lane b&3 of call b>>2.
-__device__ __forceinline__ void persite_words(const SweepArgs& a, uint32_t g, bool has_q,
-                                              uint64_t& xp, uint64_t& xq)
-{
-    uint32_t lo_p = 0, hi_p = 0, lo_q = 0, hi_q = 0;
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const u32x4 o = philox4x32_10(g, a.t, 2u * (uint32_t)j + (uint32_t)a.parity, 0u, a.k0, a.k1);
-        const uint32_t bits_p = (uint32_t)(o.v0 < a.thr_p) | ((uint32_t)(o.v1 < a.thr_p) << 1) |
-                                ((uint32_t)(o.v2 < a.thr_p) << 2) | ((uint32_t)(o.v3 < a.thr_p) << 3);
-        if (j < 8) lo_p |= bits_p << (4 * j); else hi_p |= bits_p << (4 * (j - 8));
-        if (has_q) {
-            const uint32_t bits_q = (uint32_t)(o.v0 < a.thr_q) | ((uint32_t)(o.v1 < a.thr_q) << 1) |
-                                    ((uint32_t)(o.v2 < a.thr_q) << 2) | ((uint32_t)(o.v3 < a.thr_q) << 3);
-            if (j < 8) lo_q |= bits_q << (4 * j); else hi_q |= bits_q << (4 * (j - 8));
-        }
-    }
-    xp = ((uint64_t)lo_p | ((uint64_t)hi_p << 32)) | a.all_p;
-    xq = has_q ? (((uint64_t)lo_q | ((uint64_t)hi_q << 32)) | a.all_q) : 0;
-}
-
-template <int N>
-__device__ __forceinline__ uint32_t rot_down(uint32_t v)  // bit i <- bit (i+1) mod N
-{
-    if constexpr (N == 1) return v;
-    constexpr uint32_t mask = (N == 32) ? 0xffffffffu : ((1u << N) - 1u);
-    return ((v >> 1) | (v << (N - 1))) & mask;
-}
-
-template <int N>
-__device__ __forceinline__ uint32_t rot_up(uint32_t v)  // bit i <- bit (i-1) mod N
-{
-    if constexpr (N == 1) return v;
-    constexpr uint32_t mask = (N == 32) ? 0xffffffffu : ((1u << N) - 1u);
-    return ((v << 1) | (v >> (N - 1))) & mask;
-}
-
 template <int G, int I, XiMode MODE, bool HASQ>
 __global__ __launch_bounds__(kBlock) void halfstep_kernel(SweepArgs a)
 {
-    static_assert(G >= 1 && G <= 64 && (G & (G - 1)) == 0, "G must be a power of two <= 64");
-    static_assert(I >= 1 && I <= 32, "I words per lane");
     constexpr int kRowsPerWave = 64 / G;
-
     const int lane = threadIdx.x & 63;
-    const int gl = lane & (G - 1);         // lane within the row group
-    const int gbase = lane & ~(G - 1);     // first lane of the row group
     const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-    const int64_t y_raw = wave * kRowsPerWave + lane / G;
-    const bool active = y_raw < a.Y;       // uniform within a row group
-    const int64_t y = active ? y_raw : 0;
-    const int64_t yn = (y + 1) & (a.Y - 1);
-    const int par = a.parity;
-    const bool shifted = ((par ^ (int)(y & 1)) != 0);
-
-    uint64_t* const sxP = a.S + (int64_t)(0 * 2 + par) * a.plane + y * a.W;        // x-, this parity
-    uint64_t* const syP = a.S + (int64_t)(1 * 2 + par) * a.plane + y * a.W;        // y-, this parity
-    uint64_t* const syQ = a.S + (int64_t)(1 * 2 + (1 - par)) * a.plane + yn * a.W; // y+ (row y+1)
-    uint64_t* const sxQ = a.S + (int64_t)(0 * 2 + (1 - par)) * a.plane + y * a.W;  // x+ (same row)
-
-    uint64_t A[I], B[I], C[I], D[I];
-#pragma unroll
-    for (int i = 0; i < I; ++i) {
-        const int w = i * G + gl;
-        A[i] = sxP[w];
-        B[i] = syP[w];
-        C[i] = syQ[w];
-        D[i] = sxQ[w];
-    }
-
-    // x+ slopes aligned with this row's sites.
-    uint64_t XP[I];
-    if constexpr (G == 1 && I == 1) {
-        const int nb = a.nb;
-        XP[0] = shifted ? ((D[0] >> 1) | ((D[0] & 1ull) << (nb - 1))) : D[0];
-    } else {
-        uint32_t lsb = 0;  // bit i: bit 0 of this lane's slot-i word
-#pragma unroll
-        for (int i = 0; i < I; ++i) lsb |= (uint32_t)(D[i] & 1ull) << i;
-        uint32_t nxt = lsb;
-        if constexpr (G > 1) nxt = (uint32_t)__shfl((int)lsb, gbase | ((gl + 1) & (G - 1)));
-        // The last lane of the group continues in slot i+1 of the first lane.
-        if (gl == G - 1) nxt = rot_down<I>(nxt);
-#pragma unroll
-        for (int i = 0; i < I; ++i)
-            XP[i] = shifted ? ((D[i] >> 1) | ((uint64_t)((nxt >> i) & 1u) << 63)) : D[i];
-    }
-
-    uint64_t M[I];
-    uint64_t mp0 = 0, mq0 = 0;
-#pragma unroll
-    for (int i = 0; i < I; ++i) {
-        const uint32_t g = (uint32_t)(y * a.W + i * G + gl);
-        uint64_t xip, xiq;
-        if constexpr (MODE == XiMode::Mask) {
-            mask_words(a, g, HASQ, xip, xiq);
-        } else if constexpr (MODE == XiMode::PerSite) {
-            persite_words(a, g, HASQ, xip, xiq);
-        } else {
-            xip = a.xi_p[g];
-            xiq = a.xi_q[g];
-        }
-        const uint64_t mp = xip & ~A[i] & ~B[i] & XP[i] & C[i];
-        const uint64_t mq = HASQ ? (xiq & A[i] & B[i] & ~XP[i] & ~C[i]) : 0ull;
-        if (i == 0) { mp0 = mp; mq0 = mq; }
-        M[i] = mp | mq;
-        A[i] ^= M[i];
-        B[i] ^= M[i];
-        C[i] ^= M[i];
-    }
-
-    // Apply m to the x+ slopes; in shifted rows bit k of m belongs to bit k+1.
-    if constexpr (G == 1 && I == 1) {
-        const int nb = a.nb;
-        const uint64_t valid = (nb == 64) ? ~0ull : ((1ull << nb) - 1ull);
-        D[0] ^= shifted ? (((M[0] << 1) | (M[0] >> (nb - 1))) & valid) : M[0];
-    } else {
-        uint32_t msb = 0;  // bit i: top bit of this lane's slot-i mask
-#pragma unroll
-        for (int i = 0; i < I; ++i) msb |= (uint32_t)(M[i] >> 63) << i;
-        uint32_t prv = msb;
-        if constexpr (G > 1) prv = (uint32_t)__shfl((int)msb, gbase | ((gl - 1) & (G - 1)));
-        // The first lane of the group continues from slot i-1 of the last lane.
-        if (gl == 0) prv = rot_up<I>(prv);
-#pragma unroll
-        for (int i = 0; i < I; ++i)
-            D[i] ^= shifted ? ((M[i] << 1) | (uint64_t)((prv >> i) & 1u)) : M[i];
-    }
-
-    if (active) {
-#pragma unroll
-        for (int i = 0; i < I; ++i) {
-            const int w = i * G + gl;
-            sxP[w] = A[i];
-            syP[w] = B[i];
-            syQ[w] = C[i];
-            sxQ[w] = D[i];
-        }
-        // Site (0,0) is bit 0 of word 0 of row 0 in the even sublattice.
-        if (par == 0 && y == 0 && gl == 0) {
-            const int64_t dh = 2 * (int64_t)(mp0 & 1ull) - 2 * (int64_t)(mq0 & 1ull);
-            if (dh != 0) *a.h0 += dh;
-        }
-    }
+    halfstep_rows<G, I, MODE, HASQ>(a, a.S, wave * kRowsPerWave + lane / G, lane);
 }
 
 template <int G, int I>

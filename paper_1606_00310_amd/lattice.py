@@ -34,8 +34,10 @@ class Lattice:
         self._ctx = ctx
 
     # ------------------------------------------------------------------ steps
-    def step(self, n_mcs: int, p: float, q: float = 0.0, force_persite: bool = False):
-        flags = L.SCA_FORCE_PERSITE if force_persite else 0
+    def step(self, n_mcs: int, p: float, q: float = 0.0, force_persite: bool = False, graph: bool = False):
+        """Advance n_mcs MCS.  graph=True captures the 2*n_mcs half-step
+        launches into one hipGraph, launches it once and waits for it."""
+        flags = (L.SCA_FORCE_PERSITE if force_persite else 0) | (L.SCA_STEP_GRAPH if graph else 0)
         L.check(L.lib().sca_step_ex(self._ctx, int(n_mcs), float(p), float(q), flags), "sca_step")
         return self
 

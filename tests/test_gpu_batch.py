@@ -1,0 +1,163 @@
+"""Ensembles in one persistent launch: every realization bit-identical to its
+solo run (and to the oracle), under every launch configuration; admission by
+arena budget; graph-captured solo runs."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sca():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1606_00310_amd as P
+
+    P.lib()
+    return P
+
+
+def _reals():
+    from paper_1606_00310_amd.batch import Realization as R
+
+    return [
+        R(64, 64, 0.5, 0.0, 37, 1001), R(128, 128, 0.75, 0.0, 23, 1002), R(256, 256, 0.9375, 0.0, 11, 1003),
+        R(512, 512, 0.5, 0.0, 6, 1004), R(1024, 1024, 0.75, 0.0, 4, 1005), R(2048, 2048, 0.9375, 0.0, 3, 1006),
+        R(4, 4, 0.5, 0.5, 50, 7), R(8, 32, 0.93, 0.07, 19, 8), R(4096, 16, 0.3, 0.0, 9, 9),
+        R(8192, 8, 0.75, 0.25, 13, 10), R(32, 1024, 1.0, 0.0, 17, 11), R(128, 4, 0.5, 0.0, 0, 12),
+        R(256, 64, 0.5, 0.0, 21, 13, True), R(64, 4096, 0.1875, 0.0, 8, 2**40 + 5), R(16, 16, 0.0, 1.0, 5, 14),
+        R(512, 128, 0.9375, 0.0625, 12, 15),
+    ]
+
+
+def _solo(sca, r):
+    lat = sca.Lattice(r.X, r.Y, seed=r.seed)
+    lat.step(r.n_mcs, r.p, r.q, force_persite=r.force_persite)
+    torch.cuda.synchronize()
+    return lat
+
+
+@pytest.fixture(scope="module")
+def solo_states(sca):
+    out = []
+    for r in _reals():
+        lat = _solo(sca, r)
+        out.append((lat.slopes.clone(), lat.meta()[1], lat.roughness()))
+        lat.close()
+    return out
+
+
+CONFIGS = [
+    dict(block_threads=512, blocks_per_cu=2, lds_bytes=65536, order=0),
+    dict(block_threads=256, blocks_per_cu=4, lds_bytes=65536, order=1),
+    dict(block_threads=1024, blocks_per_cu=1, lds_bytes=0, order=0),
+    dict(block_threads=512, blocks_per_cu=1, lds_bytes=16384, order=1),
+    dict(block_threads=256, blocks_per_cu=8, lds_bytes=4096, order=0),
+]
+
+
+@pytest.mark.parametrize("cfg", CONFIGS, ids=lambda c: "b{block_threads}-c{blocks_per_cu}-l{lds_bytes}-o{order}".format(**c))
+@pytest.mark.parametrize("epoch", [5, 1000])
+def test_batch_equals_solo(sca, solo_states, cfg, epoch):
+    from paper_1606_00310_amd.batch import Batch, state_bytes
+
+    reals = _reals()
+    _say(f"[batch] cfg={cfg} epoch={epoch}")
+    arena = sum(state_bytes(r.X, r.Y) for r in reals)
+    b = Batch(max_slots=len(reals), arena_bytes=arena, config=cfg)
+    slots = b.admit(reals)
+    while b.run(epoch):
+        pass
+    torch.cuda.synchronize()
+    for r, s, (ref, h0, mom) in zip(reals, slots, solo_states):
+        S, h = b.state(s)
+        assert torch.equal(S, ref), r
+        assert int(h[0]) == h0, r
+        assert b.info(s).t == r.n_mcs
+        assert b.roughness(s) == mom
+    b.close()
+
+
+def test_batch_matches_oracle(orc, sca):
+    from paper_1606_00310_amd.batch import Batch, state_bytes
+
+    reals = [r for r in _reals() if r.sites <= 1 << 16]
+    b = Batch(max_slots=len(reals), arena_bytes=sum(state_bytes(r.X, r.Y) for r in reals))
+    slots = b.admit(reals)
+    while b.run(7):
+        pass
+    torch.cuda.synchronize()
+    for r, s in zip(reals, slots):
+        st = orc.flat(r.X, r.Y)
+        orc.run(st, r.n_mcs, r.p, r.q, seed=r.seed, force_persite=r.force_persite)
+        S, h = b.state(s)
+        assert np.array_equal(S.cpu().numpy().view(np.uint64), orc.pack(st)), r
+        assert int(h[0]) == st.h0
+    b.close()
+
+
+def test_admission_budget_and_reuse(sca):
+    from paper_1606_00310_amd import ScaError
+    from paper_1606_00310_amd.batch import Batch, Realization as R, state_bytes
+
+    big = R(1024, 1024, 0.5, 0.0, 3, 1)
+    small = R(64, 64, 0.5, 0.0, 5, 2)
+    b = Batch(max_slots=4, arena_bytes=2 * state_bytes(1024, 1024))
+    s1 = b.admit([big])
+    assert b.try_admit([big, big]) is None          # all or none: not enough arena
+    s2 = b.admit([big])
+    assert b.try_admit([small]) is None              # arena full
+    b.release(s1[0])
+    s3 = b.admit([small, small, small])              # slots 4 in total now used: big + 3 small
+    assert b.try_admit([small]) is None              # no slot left
+    with pytest.raises(ScaError):
+        b.admit([R(100, 64, 0.5, 0.0, 1, 1)])        # invalid size
+    while b.run(2):
+        pass
+    lat = sca.Lattice(64, 64, seed=2)
+    lat.step(5, 0.5)
+    for s in s3:
+        assert torch.equal(b.state(s)[0], lat.slopes)
+    ref_big = sca.Lattice(1024, 1024, seed=1)
+    ref_big.step(3, 0.5)
+    assert torch.equal(b.state(s2[0])[0], ref_big.slopes)
+    b.close()
+
+
+def test_late_admission_matches_solo(sca):
+    """Realizations admitted while others are mid-run end bit-identical to
+    their solo runs (the continuous-batching case)."""
+    from paper_1606_00310_amd.batch import Batch, Realization as R, state_bytes
+
+    first = [R(256, 256, 0.75, 0.0, 40, 100 + i) for i in range(3)]
+    late = [R(128, 512, 0.9375, 0.0, 25, 200 + i) for i in range(3)]
+    b = Batch(max_slots=8, arena_bytes=sum(state_bytes(r.X, r.Y) for r in first + late))
+    s_first = b.admit(first)
+    b.run(10)
+    b.run(10)
+    s_late = b.admit(late)
+    while b.run(10):
+        pass
+    torch.cuda.synchronize()
+    for r, s in zip(first + late, s_first + s_late):
+        assert torch.equal(b.state(s)[0], _solo(sca, r).slopes), r
+    b.close()
+
+
+@pytest.mark.parametrize("X,Y,p,q", [(64, 64, 0.5, 0.0), (2048, 2048, 0.9375, 0.0), (512, 32, 0.93, 0.07)])
+def test_graph_step_equals_plain(sca, X, Y, p, q):
+    a = sca.Lattice(X, Y, seed=77)
+    b = sca.Lattice(X, Y, seed=77)
+    a.step(33, p, q)
+    b.step(33, p, q, graph=True)
+    torch.cuda.synchronize()
+    assert torch.equal(a.slopes, b.slopes) and a.meta() == b.meta()
