@@ -20,13 +20,16 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 COUNTERS = os.path.join(ROOT, "profiles", "halfstep_65536x65536_p1_counters.json")
-SWEEP_SRC = os.path.join(ROOT, "paper_1606_00310_amd", "csrc", "sweep.hip")
+SWEEP_SRC = [os.path.join(ROOT, "paper_1606_00310_amd", "csrc", f)
+             for f in ("sweep.hip", "halfstep.hpp", "philox.hpp", "sca_internal.hpp")]
 
 
 def _ensure_built():
@@ -38,9 +41,12 @@ def _ensure_built():
         __graft_entry__.build()
 
 
-def _sha(path):
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+def _sha(paths):
+    h = hashlib.sha256()
+    for path in paths:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def _traffic(bytes_per_launch_alg):
@@ -93,6 +99,108 @@ def cpu_baseline(X, Y, p, q, seed, rows, budget_s, max_mcs=200):
                       f"in {dt:.1f} s"}
 
 
+def bench_ensemble(torch, P, n=4096, solo_per_L=3, tune_sample=512, tune_mcs=100):
+    """The 4096-realization ensemble in one persistent launch vs one launch
+    (graph-captured MCS loop) per realization, and a serving run."""
+    from paper_1606_00310_amd import autotune, serve
+    from paper_1606_00310_amd.batch import Batch, Realization, state_bytes
+    from paper_1606_00310_amd.inputs import ensemble, poisson_arrivals
+
+    members = ensemble(n)
+    reals = [Realization(m.L, m.L, m.p, 0.0, m.n_mcs, m.seed) for m in members]
+    work = sum(r.sites * r.n_mcs for r in reals)
+    sample = [Realization(r.X, r.Y, r.p, r.q, min(r.n_mcs, tune_mcs), r.seed) for r in reals[:tune_sample]]
+    cfg, table = autotune.autotune(sample, cache_path=None)
+
+    b = Batch(max_slots=len(reals), arena_bytes=sum(state_bytes(r.X, r.Y) for r in reals), config=cfg)
+    b.admit(reals)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(b.stream)
+    launches = 0
+    while b.run(max(r.n_mcs for r in reals)):
+        launches += 1
+    end.record(b.stream)
+    end.synchronize()
+    batched_s = start.elapsed_time(end) / 1e3
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+
+    # one realization at a time through the single-lattice API, a stratified
+    # sample of each lattice size, timed with the MCS loop graph-captured
+    # (capture + instantiate + one launch) and with plain launches
+    by_L = {}
+    for r in reals:
+        by_L.setdefault(r.X, []).append(r)
+    est = {"graph": 0.0, "plain": 0.0}
+    per_L = {}
+    for L_, group in sorted(by_L.items()):
+        pick = group[:solo_per_L]
+        upd = sum(r.sites * r.n_mcs for r in pick)
+        tot_upd = sum(r.sites * r.n_mcs for r in group)
+        row = {}
+        for mode in ("graph", "plain"):
+            t_sum = 0.0
+            for r in pick:
+                lat = P.Lattice(r.X, r.Y, seed=r.seed)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                lat.step(r.n_mcs, r.p, r.q, graph=(mode == "graph"))
+                torch.cuda.synchronize()
+                t_sum += time.perf_counter() - t0
+                lat.close()
+            rate = upd / t_sum
+            est[mode] += tot_upd / rate
+            row[mode] = rate
+        per_L[str(L_)] = {"realizations": len(group), "sampled": len(pick),
+                          "solo_graph_updates_per_s": row["graph"], "solo_plain_updates_per_s": row["plain"]}
+    solo_s = min(est.values())
+    out = {"realizations": len(reals), "site_updates": work,
+           "batched": {"seconds": batched_s, "value": work / batched_s, "unit": "site updates/s",
+                       "launches": launches, "config": cfg},
+           "solo_estimate": {"seconds_graph": est["graph"], "seconds_plain": est["plain"],
+                             "value": work / solo_s, "unit": "site updates/s", "per_L": per_L,
+                             "method": f"{solo_per_L} realizations per lattice size timed one by one, "
+                                       "scaled by each size's total work"},
+           "speedup_vs_solo": solo_s / batched_s,
+           "autotune": [{"config": c, "ms": round(t * 1e3, 3)} for c, t in table]}
+
+    # serving: Poisson arrivals of small ensembles at 0.8x the measured capacity
+    rng = np.random.default_rng(4242)
+    n_req = 400
+    reqs = []
+    seed = 5_000_000
+    for i in range(n_req):
+        k = int(rng.integers(1, 5))
+        rs = []
+        for _ in range(k):
+            m = members[int(rng.integers(len(members)))]
+            rs.append(Realization(m.L, m.L, m.p, 0.0, m.n_mcs, seed))
+            seed += 1
+        reqs.append(serve.Request(i, rs))
+    mean_work = sum(r.work for r in reqs) / n_req
+    capacity_rps = (work / batched_s) / mean_work
+    rate = 0.8 * capacity_rps
+    arr = poisson_arrivals(n_req, rate, rng_seed=99)
+    for r, a in zip(reqs, arr):
+        r.arrival = float(a)
+    budget = 16 << 30
+    sb = Batch(max_slots=1024, arena_bytes=budget, config=cfg)
+    srv = serve.Server(serve.BatchBackend(sb, keep_states=False), mcs_epoch=100)
+    t0 = time.perf_counter()
+    done = srv.serve(reqs)
+    wall = time.perf_counter() - t0
+    sb.close()
+    served = sum(r.work for r in done)
+    out["serving"] = {"requests": n_req, "arrival_rate_per_s": rate, "capacity_requests_per_s": capacity_rps,
+                      "hbm_budget_bytes": budget, "mcs_epoch": 100, "epochs": srv.epochs,
+                      "throughput": served / wall, "unit": "site updates/s", "wall_s": wall,
+                      "latency": serve.latency_stats(done)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +210,7 @@ def main():
     ap.add_argument("--no-paths", action="store_true", help="skip the secondary paths")
     ap.add_argument("--cpu-rows", type=int, default=16384)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the batched ensemble and serving runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (torch copy_) three times, the known-size "
                          "reference for HBM byte counters")
@@ -158,6 +267,9 @@ def main():
             paths[wk.name] = {"value": rate, "unit": "site updates/s", "steps": steps,
                               "hbm_frac_1B_per_update": round(rate / (HBM_PEAK_GBS * 1e9), 4)}
         out["paths"] = paths
+
+    if not args.no_ensemble:
+        out["ensemble"] = bench_ensemble(torch, P)
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w.X, w.Y, w.p, w.q, w.seed, args.cpu_rows, args.cpu_seconds)

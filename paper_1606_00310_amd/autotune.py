@@ -1,0 +1,101 @@
+"""Autotuner for the persistent ensemble kernel.
+
+It times each launch configuration (workgroup size, workgroups per compute
+unit, LDS budget and processing order) on a sample of the ensemble, checks
+that every configuration leaves bit-identical states, and keeps the fastest.
+The choice is cached in a JSON file keyed by the device name and the sample's
+signature.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+
+import torch
+
+from .batch import Batch, state_bytes
+
+LDS_PER_CU = 160 * 1024
+
+CANDIDATES = [
+    dict(block_threads=bt, blocks_per_cu=bpc, lds_bytes=lds, order=order)
+    for bt in (256, 512, 1024)
+    for bpc in (1, 2, 4)
+    for lds in (0, 16384, 65536)
+    for order in (0,)
+    if bpc * lds <= LDS_PER_CU and bt * bpc <= 2048
+]
+
+DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_batch.json")
+
+
+def signature(reals) -> str:
+    h = hashlib.sha256()
+    for r in reals:
+        h.update(f"{r.X},{r.Y},{r.p},{r.q},{r.n_mcs},{r.seed},{int(r.force_persite)};".encode())
+    return h.hexdigest()[:16]
+
+
+def _digest(batch, slots) -> str:
+    h = hashlib.sha256()
+    for s in slots:
+        S, h0 = batch.state(s)
+        h.update(S.cpu().numpy().tobytes())
+        h.update(h0.cpu().numpy().tobytes())
+    return h.hexdigest()
+
+
+def time_config(reals, cfg, epoch=None, device="cuda"):
+    """Seconds for one epoch over the sample with this configuration, and a
+    digest of the final states."""
+    b = Batch(max_slots=len(reals), arena_bytes=sum(state_bytes(r.X, r.Y) for r in reals), device=device,
+              config=cfg)
+    slots = b.admit(reals)
+    torch.cuda.synchronize()
+    epoch = epoch or max(r.n_mcs for r in reals)
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(b.stream)
+    while b.run(epoch):
+        pass
+    end.record(b.stream)
+    end.synchronize()
+    secs = start.elapsed_time(end) / 1e3
+    digest = _digest(b, slots)
+    b.close()
+    return secs, digest
+
+
+def autotune(reals, candidates=CANDIDATES, cache_path: str | None = DEFAULT_CACHE, force: bool = False,
+             verbose: bool = False):
+    """Returns (best config, table of (config, seconds)).  Raises if two
+    configurations disagree on any bit of any final state."""
+    dev = torch.cuda.get_device_name()
+    key = f"{dev}|{signature(reals)}"
+    if cache_path and not force and os.path.exists(cache_path):
+        with open(cache_path) as f:
+            cache = json.load(f)
+        if key in cache:
+            return cache[key]["best"], cache[key]["table"]
+    table = []
+    ref = None
+    for cfg in candidates:
+        secs, digest = time_config(reals, cfg)
+        if ref is None:
+            ref = digest
+        elif digest != ref:
+            raise RuntimeError(f"configuration {cfg} changed the results")
+        table.append((cfg, secs))
+        if verbose:
+            print(f"  {cfg} {secs * 1e3:.2f} ms", flush=True)
+    best = min(table, key=lambda x: x[1])[0]
+    if cache_path:
+        cache = {}
+        if os.path.exists(cache_path):
+            with open(cache_path) as f:
+                cache = json.load(f)
+        cache[key] = {"best": best, "table": table}
+        with open(cache_path, "w") as f:
+            json.dump(cache, f, indent=1)
+    return best, table

@@ -161,3 +161,32 @@ def test_graph_step_equals_plain(sca, X, Y, p, q):
     b.step(33, p, q, graph=True)
     torch.cuda.synchronize()
     assert torch.equal(a.slopes, b.slopes) and a.meta() == b.meta()
+
+
+def test_serving_mix_equals_alone(sca):
+    """Requests arriving while others run are admitted as slots free up; every
+    served realization equals its solo run bit for bit."""
+    from paper_1606_00310_amd import serve
+    from paper_1606_00310_amd.batch import Batch, Realization as R, state_bytes
+
+    reqs = []
+    seed = 900
+    sizes = [(64, 3), (256, 1), (128, 2), (512, 1), (64, 4), (1024, 1), (32, 2), (256, 2)]
+    for i, (L, k) in enumerate(sizes):
+        rs = []
+        for j in range(k):
+            rs.append(R(L, L, (0.5, 0.75, 0.9375)[(i + j) % 3], 0.0, 15 + 7 * ((i * 3 + j) % 5), seed))
+            seed += 1
+        reqs.append(serve.Request(i, rs, arrival=0.0005 * i))
+    budget = state_bytes(1024, 1024) + 4 * state_bytes(256, 256)   # forces waiting
+    b = Batch(max_slots=6, arena_bytes=budget)
+    srv = serve.Server(serve.BatchBackend(b), mcs_epoch=6)
+    done = srv.serve(reqs)
+    assert len(done) == len(reqs)
+    for req in done:
+        for r, res in zip(req.realizations, req.results):
+            lat = _solo(sca, r)
+            assert torch.equal(res["slopes"], lat.slopes), r
+            assert res["h0"] == lat.meta()[1]
+            assert res["moments"] == lat.roughness()
+    b.close()
