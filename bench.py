@@ -99,7 +99,7 @@ def cpu_baseline(X, Y, p, q, seed, rows, budget_s, max_mcs=200):
                       f"in {dt:.1f} s"}
 
 
-def bench_ensemble(torch, P, n=4096, solo_per_L=3, tune_sample=512, tune_mcs=100):
+def bench_ensemble(torch, P, n=4096, solo_per_L=3, tune_sample=512, tune_mcs=100, serving=True, solo=True):
     """The 4096-realization ensemble in one persistent launch vs one launch
     (graph-captured MCS loop) per realization, and a serving run."""
     from paper_1606_00310_amd import autotune, serve
@@ -127,6 +127,13 @@ def bench_ensemble(torch, P, n=4096, solo_per_L=3, tune_sample=512, tune_mcs=100
     b.close()
     del b
     torch.cuda.empty_cache()
+
+    out = {"realizations": len(reals), "site_updates": work,
+           "batched": {"seconds": batched_s, "value": work / batched_s, "unit": "site updates/s",
+                       "launches": launches, "config": cfg},
+           "autotune": [{"config": c, "ms": round(t * 1e3, 3)} for c, t in table]}
+    if not solo:
+        return out
 
     # one realization at a time through the single-lattice API, a stratified
     # sample of each lattice size, timed with the MCS loop graph-captured
@@ -157,15 +164,13 @@ def bench_ensemble(torch, P, n=4096, solo_per_L=3, tune_sample=512, tune_mcs=100
         per_L[str(L_)] = {"realizations": len(group), "sampled": len(pick),
                           "solo_graph_updates_per_s": row["graph"], "solo_plain_updates_per_s": row["plain"]}
     solo_s = min(est.values())
-    out = {"realizations": len(reals), "site_updates": work,
-           "batched": {"seconds": batched_s, "value": work / batched_s, "unit": "site updates/s",
-                       "launches": launches, "config": cfg},
-           "solo_estimate": {"seconds_graph": est["graph"], "seconds_plain": est["plain"],
+    out.update({"solo_estimate": {"seconds_graph": est["graph"], "seconds_plain": est["plain"],
                              "value": work / solo_s, "unit": "site updates/s", "per_L": per_L,
                              "method": f"{solo_per_L} realizations per lattice size timed one by one, "
                                        "scaled by each size's total work"},
-           "speedup_vs_solo": solo_s / batched_s,
-           "autotune": [{"config": c, "ms": round(t * 1e3, 3)} for c, t in table]}
+           "speedup_vs_solo": solo_s / batched_s})
+    if not serving:
+        return out
 
     # serving: Poisson arrivals of small ensembles at 0.8x the measured capacity
     rng = np.random.default_rng(4242)
@@ -188,14 +193,16 @@ def bench_ensemble(torch, P, n=4096, solo_per_L=3, tune_sample=512, tune_mcs=100
         r.arrival = float(a)
     budget = 16 << 30
     sb = Batch(max_slots=1024, arena_bytes=budget, config=cfg)
-    srv = serve.Server(serve.BatchBackend(sb, keep_states=False), mcs_epoch=100)
+    quota = 100 * 2048 * 2048  # site updates per realization per epoch: 100 MCS of the largest lattice
+    srv = serve.Server(serve.BatchBackend(sb, keep_states=False), work_quota=quota)
     t0 = time.perf_counter()
     done = srv.serve(reqs)
     wall = time.perf_counter() - t0
     sb.close()
     served = sum(r.work for r in done)
     out["serving"] = {"requests": n_req, "arrival_rate_per_s": rate, "capacity_requests_per_s": capacity_rps,
-                      "hbm_budget_bytes": budget, "mcs_epoch": 100, "epochs": srv.epochs,
+                      "hbm_budget_bytes": budget, "epoch_site_updates_per_realization": quota,
+                      "epochs": srv.epochs,
                       "throughput": served / wall, "unit": "site updates/s", "wall_s": wall,
                       "latency": serve.latency_stats(done)}
     return out
@@ -211,6 +218,7 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=16384)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched ensemble and serving runs")
+    ap.add_argument("--ensemble-only", action="store_true", help="only the batched ensemble (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (torch copy_) three times, the known-size "
                          "reference for HBM byte counters")
@@ -234,6 +242,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         torch.cuda.empty_cache()
+
+    if args.ensemble_only:
+        print(json.dumps({"ensemble": bench_ensemble(torch, P, serving=False, solo=False)}), flush=True)
+        return
 
     w = HEADLINE
     K, Wm = args.steps, args.warmup

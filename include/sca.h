@@ -211,6 +211,13 @@ int sca_batch_admit(sca_batch* b, const sca_req* reqs, int32_t n, int32_t* slots
  * (optional) receives the number of realizations that ran.  Asynchronous. */
 int sca_batch_run(sca_batch* b, int64_t mcs_epoch, int32_t* active_out);
 
+/* One epoch with a work quota instead of a fixed MCS count: every admitted
+ * realization with work left advances max(1, site_updates / (X*Y)) MCS
+ * (clamped to its budget), so small lattices cover many MCS in the time a
+ * large one covers a few.  Results do not depend on the epoch lengths.
+ * Asynchronous. */
+int sca_batch_run_work(sca_batch* b, int64_t site_updates, int32_t* active_out);
+
 /* Slot description; SCA_EINVAL for a free slot.  t is the MCS count the slot
  * will have reached once the enqueued epochs have run. */
 int sca_batch_slot(const sca_batch* b, int32_t slot, sca_slot_info* out);

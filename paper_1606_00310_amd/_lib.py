@@ -74,6 +74,7 @@ _SIGNATURES = {
     "sca_batch_get_config": ([_vp, ctypes.POINTER(BatchConfig)], _int),
     "sca_batch_admit": ([_vp, ctypes.POINTER(Req), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)], _int),
     "sca_batch_run": ([_vp, _i64, ctypes.POINTER(ctypes.c_int32)], _int),
+    "sca_batch_run_work": ([_vp, _i64, ctypes.POINTER(ctypes.c_int32)], _int),
     "sca_batch_slot": ([_vp, ctypes.c_int32, ctypes.POINTER(SlotInfo)], _int),
     "sca_batch_roughness": ([_vp, ctypes.c_int32, _i64p, _dblp], _int),
     "sca_batch_release": ([_vp, ctypes.c_int32], _int),

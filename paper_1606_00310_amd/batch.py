@@ -96,6 +96,13 @@ class Batch:
         L.check(L.lib().sca_batch_run(self._b, int(mcs_epoch), ctypes.byref(active)), "sca_batch_run")
         return int(active.value)
 
+    def run_work(self, site_updates: int) -> int:
+        """One epoch in which each realization advances max(1, site_updates /
+        (X*Y)) MCS (asynchronous); returns how many advanced."""
+        active = ctypes.c_int32()
+        L.check(L.lib().sca_batch_run_work(self._b, int(site_updates), ctypes.byref(active)), "sca_batch_run_work")
+        return int(active.value)
+
     def info(self, slot: int) -> L.SlotInfo:
         s = L.SlotInfo()
         L.check(L.lib().sca_batch_slot(self._b, int(slot), ctypes.byref(s)), "sca_batch_slot")

@@ -714,9 +714,14 @@ int sca_batch_admit(sca_batch* b, const sca_req* reqs, int32_t n, int32_t* slots
     return SCA_OK;
 }
 
-int sca_batch_run(sca_batch* b, int64_t mcs_epoch, int32_t* active_out)
+}  // extern "C"
+
+namespace {
+
+// One epoch in which slot s advances mcs_of(s) MCS (clamped to its budget).
+template <typename F>
+int batch_epoch(sca_batch* b, F mcs_of, int32_t* active_out)
 {
-    if (!b || mcs_epoch < 0) return SCA_EINVAL;
     if (b->failed) return SCA_ESTATE;
     DeviceGuard dg(b->device);
     if (!dg.ok) return bfail(b);
@@ -725,14 +730,18 @@ int sca_batch_run(sca_batch* b, int64_t mcs_epoch, int32_t* active_out)
     b->staged_pending = false;
     int32_t count = 0, hi = -1;
     std::vector<std::pair<int64_t, int32_t>> work;
+    std::vector<int64_t> runs((size_t)b->max_slots, 0);
     for (int32_t slot = 0; slot < b->max_slots; ++slot) {
         SlotHost& s = b->slots[(size_t)slot];
         if (!s.used) continue;
         const int64_t left = s.req.n_mcs - s.t;
-        const int64_t run = left < mcs_epoch ? left : mcs_epoch;
+        int64_t run = mcs_of(s);
+        if (run > left) run = left;
+        if (run < 0) run = 0;
+        runs[(size_t)slot] = run;
         sca::BatchDesc d = s.desc;
         d.t = (uint32_t)s.t;
-        d.n_run = (uint32_t)(run > 0 ? run : 0);
+        d.n_run = (uint32_t)run;
         b->h_desc[slot] = d;
         hi = slot;
         if (run > 0) work.emplace_back(run * s.req.X * s.req.Y, slot);
@@ -756,12 +765,30 @@ int sca_batch_run(sca_batch* b, int64_t mcs_epoch, int32_t* active_out)
     b->staged_pending = true;
     if (!b->exec && capture_epoch_graph(b) != hipSuccess) return bfail(b);
     if (hipGraphLaunch(b->exec, b->stream) != hipSuccess) return bfail(b);
-    for (const auto& w : work) {
-        SlotHost& s = b->slots[(size_t)w.second];
-        const int64_t left = s.req.n_mcs - s.t;
-        s.t += left < mcs_epoch ? left : mcs_epoch;
-    }
+    for (const auto& w : work) b->slots[(size_t)w.second].t += runs[(size_t)w.second];
     return SCA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sca_batch_run(sca_batch* b, int64_t mcs_epoch, int32_t* active_out)
+{
+    if (!b || mcs_epoch < 0) return SCA_EINVAL;
+    return batch_epoch(b, [mcs_epoch](const SlotHost&) { return mcs_epoch; }, active_out);
+}
+
+int sca_batch_run_work(sca_batch* b, int64_t site_updates, int32_t* active_out)
+{
+    if (!b || site_updates <= 0) return SCA_EINVAL;
+    return batch_epoch(
+        b,
+        [site_updates](const SlotHost& s) {
+            const int64_t q = site_updates / (s.req.X * s.req.Y);
+            return q > 0 ? q : (int64_t)1;
+        },
+        active_out);
 }
 
 int sca_batch_slot(const sca_batch* b, int32_t slot, sca_slot_info* out)

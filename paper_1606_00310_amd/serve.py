@@ -4,7 +4,9 @@ A request is an ensemble run: a list of independent realizations (lattice
 size, p, q, MCS budget, seed).  Requests queue in arrival order.  Before
 every epoch the server admits queued requests, whole ones only, while the
 batch has free slots and free arena bytes (the HBM budget).  It then advances
-every admitted realization by up to `mcs_epoch` MCS in one persistent launch,
+every admitted realization in one persistent launch -- by a fixed number of
+MCS, or by a work quota of site updates so that small lattices finish in one
+epoch while large ones advance a few MCS --
 retires the finished ones (exact moments, final state, origin height) and
 frees their slots and memory for the next arrivals.
 
@@ -53,6 +55,9 @@ class BatchBackend:
     def run(self, mcs_epoch):
         return self.batch.run(mcs_epoch)
 
+    def run_work(self, site_updates):
+        return self.batch.run_work(site_updates)
+
     def sync(self):
         import torch
 
@@ -74,9 +79,12 @@ class BatchBackend:
 
 
 class Server:
-    def __init__(self, backend, mcs_epoch: int = 100, clock=time.perf_counter):
+    def __init__(self, backend, mcs_epoch: int = 100, clock=time.perf_counter, work_quota: int | None = None):
+        """mcs_epoch: MCS per epoch; or, if work_quota is given, site updates
+        per realization per epoch (at least one MCS)."""
         self.backend = backend
         self.mcs_epoch = int(mcs_epoch)
+        self.work_quota = None if work_quota is None else int(work_quota)
         self.clock = clock
         self.t0 = clock()
         self.queue: deque[Request] = deque()
@@ -126,7 +134,12 @@ class Server:
         # zero-MCS realizations finish without running
         self._retire()
         self._admit()
-        active = self.backend.run(self.mcs_epoch) if self.running else 0
+        if not self.running:
+            active = 0
+        elif self.work_quota is not None:
+            active = self.backend.run_work(self.work_quota)
+        else:
+            active = self.backend.run(self.mcs_epoch)
         if active:
             self.epochs += 1
             self.backend.sync()

@@ -190,3 +190,21 @@ def test_serving_mix_equals_alone(sca):
             assert res["h0"] == lat.meta()[1]
             assert res["moments"] == lat.roughness()
     b.close()
+
+
+def test_work_quota_epochs_equal_solo(sca, solo_states):
+    from paper_1606_00310_amd.batch import Batch, state_bytes
+
+    reals = _reals()
+    b = Batch(max_slots=len(reals), arena_bytes=sum(state_bytes(r.X, r.Y) for r in reals))
+    slots = b.admit(reals)
+    epochs = 0
+    while b.run_work(3 * 256 * 256):
+        epochs += 1
+    assert epochs > 1
+    torch.cuda.synchronize()
+    for r, s, (ref, h0, mom) in zip(reals, slots, solo_states):
+        S, h = b.state(s)
+        assert torch.equal(S, ref), r
+        assert int(h[0]) == h0
+    b.close()

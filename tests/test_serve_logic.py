@@ -39,6 +39,16 @@ class FakeBackend:
         self.runs.append(active)
         return active
 
+    def run_work(self, quota):
+        active = 0
+        for v in self.used.values():
+            left = v[0].n_mcs - v[1]
+            if left > 0:
+                v[1] += min(left, max(1, quota // (v[0].X * v[0].Y)))
+                active += 1
+        self.runs.append(active)
+        return active
+
     def sync(self):
         pass
 
@@ -126,3 +136,16 @@ def test_serve_with_arrivals_and_stats():
     assert len(done) == 10
     st = latency_stats(done)
     assert st["n"] == 10 and st["p50_s"] <= st["p99_s"] <= st["max_s"]
+
+
+def test_work_quota_finishes_small_lattices_first():
+    be = FakeBackend(max_slots=4, budget=10**9)
+    srv = Server(be, clock=Clock(), work_quota=64 * 64 * 50)
+    srv.submit(Request(0, [R(256, 256, 0.5, 0.0, 40, 1)]))
+    srv.submit(Request(1, [R(64, 64, 0.5, 0.0, 40, 2)]))
+    srv.step()
+    # the 64x64 realization covers all 40 MCS in the first epoch, the 256x256 one 3
+    assert [r.rid for r in srv.completed] == [1]
+    while srv.running:
+        srv.step()
+    assert srv.completed[-1].results[0]["t"] == 40
