@@ -27,9 +27,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-COUNTERS = os.path.join(ROOT, "profiles", "halfstep_65536x65536_p1_counters.json")
+COUNTERS = os.path.join(ROOT, "profiles", "mcs_fused_65536x65536_p1_counters.json")
 SWEEP_SRC = [os.path.join(ROOT, "paper_1606_00310_amd", "csrc", f)
-             for f in ("sweep.hip", "halfstep.hpp", "philox.hpp", "sca_internal.hpp")]
+             for f in ("fused.hip", "halfstep.hpp", "philox.hpp", "sca_internal.hpp")]
 
 
 def _ensure_built():
@@ -252,13 +252,19 @@ def main():
     torch.cuda.synchronize()
     ms = time_path(torch, P, w.X, w.Y, w.p, w.q, w.seed, K, Wm)
     value = w.sites * K / (ms / 1e3)
-    launches = 2 * K
+    # Pairs of MCS run as one fused pass each (both half-steps in one sweep);
+    # an odd K adds one MCS of two half-step launches.  Every launch of either
+    # kind reads the packed state once and writes it once: X*Y/4 bytes each
+    # way.
+    fused = K % 2 == 0
+    launches = K if fused else (K - 1) + 2
     avg_ms = ms / launches
-    alg_bytes = w.sites // 2  # read X*Y/4 + write X*Y/4 bytes per half-step
-    achieved = alg_bytes / (avg_ms / 1e3) / 1e9
+    alg_bytes = w.sites // 2
+    achieved = alg_bytes * launches / (ms / 1e3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": _traffic(alg_bytes),
-                "kernel": "halfstep_kernel<64,8,Mask,false>", "alg_bytes_per_launch": alg_bytes,
+                "kernel": "mcs_fused_kernel<8,Mask,false>" if fused else "halfstep_kernel<64,8,Mask,false>",
+                "alg_bytes_per_launch": alg_bytes, "alg_bytes_per_site_update": alg_bytes / w.sites * (1 if fused else 2),
                 "avg_launch_ms": round(avg_ms, 5)}
 
     out = {

@@ -33,8 +33,9 @@
  *  - Sizes: X and Y powers of two, 4 <= X, Y <= 131072.  0 <= p, q <= 1.
  *  - Ownership: every device buffer is owned by the caller; the library keeps
  *    non-owning pointers, so the caller keeps them alive until sca_destroy.
- *    The library owns only a small device workspace (about 40*Y bytes)
- *    allocated by sca_init and freed by sca_destroy.
+ *    The library owns a small device workspace (about 40*Y bytes)
+ *    allocated by sca_init and, once the fused pass is first used, a second
+ *    state buffer of the size of S; sca_destroy frees both.
  *  - Streams: all work is enqueued on the stream given to sca_init.  Only
  *    calls that return numbers to the host synchronize that stream.
  *  - Errors: functions return SCA_OK or a negative code; an invalid argument
@@ -67,6 +68,7 @@ enum sca_status {
 /* sca_step_ex flags */
 #define SCA_FORCE_PERSITE 1u /* use per-site 32-bit compares even for dyadic p, q */
 #define SCA_STEP_GRAPH 2u    /* capture the MCS loop into one hipGraph and launch it once */
+#define SCA_NO_FUSE 4u       /* always two half-step launches per MCS (no fused pass) */
 
 /* Length of the caller-owned int64 aux buffer; aux[0] holds h(0,0). */
 #define SCA_AUX_LEN 8
@@ -87,7 +89,13 @@ int sca_init(sca_ctx** out, int64_t X, int64_t Y, uint64_t seed, void* slopes_de
 
 /* Advances n_mcs >= 0 MCS with deposition probability p and removal
  * probability q (Eq. (2)); each MCS is the even then the odd half-step
- * (Sec. I-A), t grows by n_mcs.  Asynchronous. */
+ * (Sec. I-A), t grows by n_mcs.  Asynchronous.
+ * For 8192 <= X <= 65536 pairs of MCS run as fused passes (both half-steps
+ * of an MCS in one sweep over the state, out of place into the library's
+ * second buffer and back), which halves the HBM traffic per MCS; the results
+ * are bit-identical to the two-launch form, and S holds the state when the
+ * enqueued work has run.  If the second buffer cannot be allocated the call
+ * falls back to two launches per MCS. */
 int sca_step(sca_ctx* ctx, int64_t n_mcs, double p, double q);
 
 /* sca_step with flags (SCA_FORCE_PERSITE, SCA_STEP_GRAPH).  With
@@ -124,6 +132,10 @@ int sca_autocorr(sca_ctx* ctx, const void* snap_dev, int64_t out4[4], double* c_
 
 /* Current MCS count t and origin height h(0,0).  Synchronizes. */
 int sca_get_meta(sca_ctx* ctx, int64_t* t, int64_t* h0);
+
+/* Rows per wavefront in the fused pass (a power of two >= 4 that divides Y,
+ * default 32), or 0 to disable fusion for this context. */
+int sca_set_fused_band(sca_ctx* ctx, int32_t band);
 
 /* Sets the MCS counter (for resuming from a saved state; the caller restores
  * S and aux itself).  0 <= t < 2^32. */

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libsca.so")
 SCA_OK, SCA_EINVAL, SCA_ENOMEM, SCA_EDEVICE, SCA_EOVERFLOW, SCA_ESTATE, SCA_EBUSY = 0, -1, -2, -3, -4, -5, -6
 SCA_FORCE_PERSITE = 1
 SCA_STEP_GRAPH = 2
+SCA_NO_FUSE = 4
 SCA_AUX_LEN = 8
 
 
@@ -65,6 +66,7 @@ _SIGNATURES = {
     "sca_autocorr": ([_vp, _vp, _i64p, _dblp], _int),
     "sca_get_meta": ([_vp, _i64p, _i64p], _int),
     "sca_set_time": ([_vp, _i64], _int),
+    "sca_set_fused_band": ([_vp, ctypes.c_int32], _int),
     "sca_debug_halfstep": ([_vp, _int, _vp, _vp], _int),
     "sca_debug_philox": ([_vp, _u32, _u32, _i64, _vp, _vp], _int),
     "sca_destroy": ([_vp], None),

@@ -31,6 +31,8 @@ struct sca_ctx {
     bool failed = false;
     int64_t* ws = nullptr;     // library-owned: rows[3Y], col[Y], res[8]
     hipStream_t capture = nullptr;  // private stream for hipGraph capture (created on first use)
+    uint64_t* alt = nullptr;        // library-owned second state for the fused MCS pass (first use)
+    int32_t band = 32;              // rows per wavefront in the fused pass; 0 = never fuse
 };
 
 namespace {
@@ -217,7 +219,8 @@ int sca_step_ex(sca_ctx* c, int64_t n_mcs, double p, double q, unsigned flags)
 {
     if (!c) return SCA_EINVAL;
     if (c->failed) return SCA_ESTATE;
-    if (n_mcs < 0 || !valid_prob(p) || !valid_prob(q) || (flags & ~(SCA_FORCE_PERSITE | SCA_STEP_GRAPH)))
+    if (n_mcs < 0 || !valid_prob(p) || !valid_prob(q) ||
+        (flags & ~(SCA_FORCE_PERSITE | SCA_STEP_GRAPH | SCA_NO_FUSE)))
         return SCA_EINVAL;
     if (c->t + n_mcs > (int64_t)UINT32_MAX) return SCA_EINVAL;
     if (n_mcs == 0) return SCA_OK;
@@ -248,8 +251,28 @@ int sca_step_ex(sca_ctx* c, int64_t n_mcs, double p, double q, unsigned flags)
     }
     const sca::XiMode mode = persite ? sca::XiMode::PerSite : sca::XiMode::Mask;
     const int64_t t0 = c->t;
+    // Pairs of MCS run as fused passes S -> alt -> S (one HBM pass per MCS);
+    // an odd last MCS, or lattices the fused pass does not cover, run as two
+    // in-place half-step launches.  The caller's S holds the state after every
+    // call either way.
+    bool fuse = !(flags & SCA_NO_FUSE) && c->band > 0 && n_mcs >= 2 && sca::fused_supported(c->W, c->Y, c->band);
+    if (fuse && !c->alt) {
+        if (hipMalloc(&c->alt, sizeof(uint64_t) * (size_t)(4 * c->Y * c->W)) != hipSuccess) {
+            (void)hipGetLastError();
+            c->alt = nullptr;
+            fuse = false;  // not enough memory for the second state: unfused launches
+        }
+    }
+    const int64_t n_fused = fuse ? (n_mcs & ~(int64_t)1) : 0;
     auto enqueue = [&](hipStream_t st) -> hipError_t {
-        for (int64_t i = 0; i < n_mcs; ++i) {
+        for (int64_t i = 0; i < n_fused; ++i) {
+            a.t = (uint32_t)(t0 + i);
+            const bool fwd = (i & 1) == 0;
+            const hipError_t e = sca::launch_mcs_fused(a, mode, has_q, fwd ? c->S : c->alt, fwd ? c->alt : c->S,
+                                                       c->band, st);
+            if (e != hipSuccess) return e;
+        }
+        for (int64_t i = n_fused; i < n_mcs; ++i) {
             a.t = (uint32_t)(t0 + i);
             for (int parity = 0; parity < 2; ++parity) {
                 a.parity = parity;
@@ -370,6 +393,13 @@ int sca_get_meta(sca_ctx* c, int64_t* t, int64_t* h0)
     return SCA_OK;
 }
 
+int sca_set_fused_band(sca_ctx* c, int32_t band)
+{
+    if (!c || band < 0 || (band > 0 && (band < 4 || (band & (band - 1)) != 0))) return SCA_EINVAL;
+    c->band = band;
+    return SCA_OK;
+}
+
 int sca_set_time(sca_ctx* c, int64_t t)
 {
     if (!c || t < 0 || t > (int64_t)UINT32_MAX) return SCA_EINVAL;
@@ -407,6 +437,7 @@ void sca_destroy(sca_ctx* c)
         (void)hipStreamSynchronize(c->stream);
         (void)hipFree(c->ws);
         if (c->capture) (void)hipStreamDestroy(c->capture);
+        if (c->alt) (void)hipFree(c->alt);
     }
     delete c;
 }

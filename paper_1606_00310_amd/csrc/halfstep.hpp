@@ -94,10 +94,90 @@ __device__ __forceinline__ uint32_t rot_up(uint32_t v)  // bit i <- bit (i-1) mo
     return ((v << 1) | (v >> (N - 1))) & mask;
 }
 
+// x+ slopes aligned with the sites of a row: D holds the other sublattice's
+// x-slopes of the same row (slot i = word i*G + gl).  In shifted rows bit k
+// takes bit k+1, crossing into the next word (next lane, or slot i+1 of the
+// group's first lane, wrapping at the row end).  All lanes of the wave call
+// this together (lane shuffle).
+template <int G, int I>
+__device__ __forceinline__ void align_xplus(const uint64_t (&D)[I], bool shifted, int gl, int gbase, int nb,
+                                            uint64_t (&XP)[I])
+{
+    if constexpr (G == 1 && I == 1) {
+        XP[0] = shifted ? ((D[0] >> 1) | ((D[0] & 1ull) << (nb - 1))) : D[0];
+    } else {
+        uint32_t lsb = 0;  // bit i: bit 0 of this lane's slot-i word
+#pragma unroll
+        for (int i = 0; i < I; ++i) lsb |= (uint32_t)(D[i] & 1ull) << i;
+        uint32_t nxt = lsb;
+        if constexpr (G > 1) nxt = (uint32_t)__shfl((int)lsb, gbase | ((gl + 1) & (G - 1)));
+        // The last lane of the group continues in slot i+1 of the first lane.
+        if (gl == G - 1) nxt = rot_down<I>(nxt);
+#pragma unroll
+        for (int i = 0; i < I; ++i)
+            XP[i] = shifted ? ((D[i] >> 1) | ((uint64_t)((nxt >> i) & 1u) << 63)) : D[i];
+    }
+}
+
+// Applies the update mask to the x+ slopes D; in shifted rows bit k of m
+// belongs to bit k+1 (the top bit of a word to bit 0 of the next word).  All
+// lanes of the wave call this together.
+template <int G, int I>
+__device__ __forceinline__ void apply_xplus(uint64_t (&D)[I], const uint64_t (&M)[I], bool shifted, int gl, int gbase,
+                                            int nb)
+{
+    if constexpr (G == 1 && I == 1) {
+        const uint64_t valid = (nb == 64) ? ~0ull : ((1ull << nb) - 1ull);
+        D[0] ^= shifted ? (((M[0] << 1) | (M[0] >> (nb - 1))) & valid) : M[0];
+    } else {
+        uint32_t msb = 0;  // bit i: top bit of this lane's slot-i mask
+#pragma unroll
+        for (int i = 0; i < I; ++i) msb |= (uint32_t)(M[i] >> 63) << i;
+        uint32_t prv = msb;
+        if constexpr (G > 1) prv = (uint32_t)__shfl((int)msb, gbase | ((gl - 1) & (G - 1)));
+        // The first lane of the group continues from slot i-1 of the last lane.
+        if (gl == 0) prv = rot_up<I>(prv);
+#pragma unroll
+        for (int i = 0; i < I; ++i)
+            D[i] ^= shifted ? ((M[i] << 1) | (uint64_t)((prv >> i) & 1u)) : M[i];
+    }
+}
+
+// Update masks of row y (Eqs. (3)-(5)) from the on-site x- and y- slopes A,
+// B, the y+ slopes C and the aligned x+ slopes XP, with the acceptance words
+// of sublattice a.parity at MCS a.t; A, B, C are updated in place.  mp0 and
+// mq0 return the slot-0 masks (the origin lives in bit 0 of slot 0, lane 0).
+template <int G, int I, XiMode MODE, bool HASQ>
+__device__ __forceinline__ void row_masks(const SweepArgs& a, int64_t y, int gl, uint64_t (&A)[I], uint64_t (&B)[I],
+                                          uint64_t (&C)[I], const uint64_t (&XP)[I], uint64_t (&M)[I],
+                                          uint64_t& mp0, uint64_t& mq0)
+{
+#pragma unroll
+    for (int i = 0; i < I; ++i) {
+        const uint32_t g = (uint32_t)(y * a.W + i * G + gl);
+        uint64_t xip, xiq;
+        if constexpr (MODE == XiMode::Mask) {
+            mask_words(a, g, HASQ, xip, xiq);
+        } else if constexpr (MODE == XiMode::PerSite) {
+            persite_words(a, g, HASQ, xip, xiq);
+        } else {
+            xip = a.xi_p[g];
+            xiq = a.xi_q[g];
+        }
+        const uint64_t mp = xip & ~A[i] & ~B[i] & XP[i] & C[i];
+        const uint64_t mq = HASQ ? (xiq & A[i] & B[i] & ~XP[i] & ~C[i]) : 0ull;
+        if (i == 0) { mp0 = mp; mq0 = mq; }
+        M[i] = mp | mq;
+        A[i] ^= M[i];
+        B[i] ^= M[i];
+        C[i] ^= M[i];
+    }
+}
+
 // One half-step of row y for the lanes of one row group.  S is the base of
 // S[2][2][Y][W] (global or LDS); every lane of the wave must call this
-// together (lane shuffles); lanes with active == false load row 0 and store
-// nothing.
+// together (lane shuffles); lanes of a group with y_raw >= Y load row 0 and
+// store nothing.
 template <int G, int I, XiMode MODE, bool HASQ>
 __device__ __forceinline__ void halfstep_rows(const SweepArgs& a, uint64_t* S, int64_t y_raw, int lane)
 {
@@ -125,65 +205,11 @@ __device__ __forceinline__ void halfstep_rows(const SweepArgs& a, uint64_t* S, i
         C[i] = syQ[w];
         D[i] = sxQ[w];
     }
-
-    // x+ slopes aligned with this row's sites.
-    uint64_t XP[I];
-    if constexpr (G == 1 && I == 1) {
-        const int nb = a.nb;
-        XP[0] = shifted ? ((D[0] >> 1) | ((D[0] & 1ull) << (nb - 1))) : D[0];
-    } else {
-        uint32_t lsb = 0;  // bit i: bit 0 of this lane's slot-i word
-#pragma unroll
-        for (int i = 0; i < I; ++i) lsb |= (uint32_t)(D[i] & 1ull) << i;
-        uint32_t nxt = lsb;
-        if constexpr (G > 1) nxt = (uint32_t)__shfl((int)lsb, gbase | ((gl + 1) & (G - 1)));
-        // The last lane of the group continues in slot i+1 of the first lane.
-        if (gl == G - 1) nxt = rot_down<I>(nxt);
-#pragma unroll
-        for (int i = 0; i < I; ++i)
-            XP[i] = shifted ? ((D[i] >> 1) | ((uint64_t)((nxt >> i) & 1u) << 63)) : D[i];
-    }
-
-    uint64_t M[I];
+    uint64_t XP[I], M[I];
     uint64_t mp0 = 0, mq0 = 0;
-#pragma unroll
-    for (int i = 0; i < I; ++i) {
-        const uint32_t g = (uint32_t)(y * a.W + i * G + gl);
-        uint64_t xip, xiq;
-        if constexpr (MODE == XiMode::Mask) {
-            mask_words(a, g, HASQ, xip, xiq);
-        } else if constexpr (MODE == XiMode::PerSite) {
-            persite_words(a, g, HASQ, xip, xiq);
-        } else {
-            xip = a.xi_p[g];
-            xiq = a.xi_q[g];
-        }
-        const uint64_t mp = xip & ~A[i] & ~B[i] & XP[i] & C[i];
-        const uint64_t mq = HASQ ? (xiq & A[i] & B[i] & ~XP[i] & ~C[i]) : 0ull;
-        if (i == 0) { mp0 = mp; mq0 = mq; }
-        M[i] = mp | mq;
-        A[i] ^= M[i];
-        B[i] ^= M[i];
-        C[i] ^= M[i];
-    }
-
-    // Apply m to the x+ slopes; in shifted rows bit k of m belongs to bit k+1.
-    if constexpr (G == 1 && I == 1) {
-        const int nb = a.nb;
-        const uint64_t valid = (nb == 64) ? ~0ull : ((1ull << nb) - 1ull);
-        D[0] ^= shifted ? (((M[0] << 1) | (M[0] >> (nb - 1))) & valid) : M[0];
-    } else {
-        uint32_t msb = 0;  // bit i: top bit of this lane's slot-i mask
-#pragma unroll
-        for (int i = 0; i < I; ++i) msb |= (uint32_t)(M[i] >> 63) << i;
-        uint32_t prv = msb;
-        if constexpr (G > 1) prv = (uint32_t)__shfl((int)msb, gbase | ((gl - 1) & (G - 1)));
-        // The first lane of the group continues from slot i-1 of the last lane.
-        if (gl == 0) prv = rot_up<I>(prv);
-#pragma unroll
-        for (int i = 0; i < I; ++i)
-            D[i] ^= shifted ? ((M[i] << 1) | (uint64_t)((prv >> i) & 1u)) : M[i];
-    }
+    align_xplus<G, I>(D, shifted, gl, gbase, a.nb, XP);
+    row_masks<G, I, MODE, HASQ>(a, y, gl, A, B, C, XP, M, mp0, mq0);
+    apply_xplus<G, I>(D, M, shifted, gl, gbase, a.nb);
 
     if (active) {
 #pragma unroll

@@ -34,10 +34,13 @@ class Lattice:
         self._ctx = ctx
 
     # ------------------------------------------------------------------ steps
-    def step(self, n_mcs: int, p: float, q: float = 0.0, force_persite: bool = False, graph: bool = False):
-        """Advance n_mcs MCS.  graph=True captures the 2*n_mcs half-step
-        launches into one hipGraph, launches it once and waits for it."""
-        flags = (L.SCA_FORCE_PERSITE if force_persite else 0) | (L.SCA_STEP_GRAPH if graph else 0)
+    def step(self, n_mcs: int, p: float, q: float = 0.0, force_persite: bool = False, graph: bool = False,
+             fuse: bool = True):
+        """Advance n_mcs MCS.  graph=True captures the launches into one
+        hipGraph, launches it once and waits for it; fuse=False forces two
+        half-step launches per MCS."""
+        flags = ((L.SCA_FORCE_PERSITE if force_persite else 0) | (L.SCA_STEP_GRAPH if graph else 0)
+                 | (0 if fuse else L.SCA_NO_FUSE))
         L.check(L.lib().sca_step_ex(self._ctx, int(n_mcs), float(p), float(q), flags), "sca_step")
         return self
 
@@ -91,6 +94,10 @@ class Lattice:
         t = ctypes.c_int64()
         L.check(L.lib().sca_get_meta(self._ctx, ctypes.byref(t), None), "sca_get_meta")
         return int(t.value)
+
+    def set_fused_band(self, band: int):
+        """Rows per wavefront of the fused MCS pass (0 disables fusion)."""
+        L.check(L.lib().sca_set_fused_band(self._ctx, int(band)), "sca_set_fused_band")
 
     def set_time(self, t: int):
         L.check(L.lib().sca_set_time(self._ctx, int(t)), "sca_set_time")

@@ -1,0 +1,76 @@
+"""The fused MCS pass (both half-steps in one sweep, out of place) against
+the two-launch form and the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sca():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1606_00310_amd as P
+
+    P.lib()
+    return P
+
+
+PROBS = [(0.5, 0.0, False), (0.75, 0.25, False), (0.9375, 0.0, False), (1.0, 0.0, False), (0.0, 1.0, False),
+         (0.93, 0.07, False), (0.5, 0.5, True)]
+
+
+@pytest.mark.parametrize("X,Y", [(8192, 64), (16384, 128), (32768, 64), (65536, 64), (8192, 256)])
+@pytest.mark.parametrize("p,q,persite", PROBS)
+def test_fused_vs_oracle(orc, sca, X, Y, p, q, persite):
+    _say(f"[fused] X={X} Y={Y} p={p} q={q}")
+    seed = 31 + X + Y
+    n = 6
+    lat = sca.Lattice(X, Y, seed=seed)
+    lat.step(n, p, q, force_persite=persite)
+    st = orc.flat(X, Y, track_heights=False)
+    orc.run(st, n, p, q, seed=seed, force_persite=persite)
+    torch.cuda.synchronize()
+    assert np.array_equal(lat.slopes.cpu().numpy().view(np.uint64), orc.pack(st))
+    assert lat.meta() == (st.t, st.h0)
+    assert lat.roughness()[:3] == orc.moments(st)[:3]
+
+
+@pytest.mark.parametrize("band", [4, 8, 16, 32, 64])
+@pytest.mark.parametrize("n", [1, 2, 3, 8, 11])
+def test_fused_equals_unfused(sca, band, n):
+    X, Y = 16384, 256
+    a = sca.Lattice(X, Y, seed=5)
+    b = sca.Lattice(X, Y, seed=5)
+    a.set_fused_band(band)
+    a.step(n, 0.9375, 0.0)
+    a.step(n + 1, 0.75, 0.25)
+    b.step(n, 0.9375, 0.0, fuse=False)
+    b.step(n + 1, 0.75, 0.25, fuse=False)
+    torch.cuda.synchronize()
+    assert torch.equal(a.slopes, b.slopes) and a.meta() == b.meta()
+
+
+def test_fused_graph_and_disable(sca):
+    X, Y = 65536, 128
+    a = sca.Lattice(X, Y, seed=9)
+    b = sca.Lattice(X, Y, seed=9)
+    c = sca.Lattice(X, Y, seed=9)
+    a.step(10, 0.5, 0.0, graph=True)
+    b.set_fused_band(0)
+    b.step(10, 0.5, 0.0)
+    c.step(10, 0.5, 0.0)
+    torch.cuda.synchronize()
+    assert torch.equal(a.slopes, b.slopes) and torch.equal(b.slopes, c.slopes)
+    assert a.meta() == b.meta() == c.meta()
+    with pytest.raises(sca.ScaError):
+        a.set_fused_band(12)
