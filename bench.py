@@ -62,21 +62,34 @@ def _traffic(bytes_per_launch_alg):
     return c.get("hbm_bytes_per_launch")
 
 
-def time_path(torch, P, X, Y, p, q, seed, steps, warmup, force_persite=False):
+def time_path(torch, P, X, Y, p, q, seed, steps, warmup, force_persite=False, split=None, blocking=None):
+    """Milliseconds for `steps` MCS after `warmup` MCS.  With split = m the
+    timed region is recorded as two parts, the first m MCS (whole fused passes)
+    and the rest; returns (total, first part).  blocking = (depth, band) for
+    sca_set_blocking (default: the library's automatic choice)."""
     lat = P.Lattice(X, Y, seed=seed)
+    if blocking is not None:
+        lat.set_blocking(*blocking)
     lat.step(warmup, p, q, force_persite=force_persite)
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
+    mid = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
     start.record(lat.stream)
-    lat.step(steps, p, q, force_persite=force_persite)
+    if split:
+        lat.step(split, p, q, force_persite=force_persite)
+        mid.record(lat.stream)
+        lat.step(steps - split, p, q, force_persite=force_persite)
+    else:
+        lat.step(steps, p, q, force_persite=force_persite)
     end.record(lat.stream)
     end.synchronize()
     ms = start.elapsed_time(end)
+    first = start.elapsed_time(mid) if split else None
     lat.close()
     del lat
     torch.cuda.empty_cache()
-    return ms
+    return (ms, first) if split else ms
 
 
 def cpu_baseline(X, Y, p, q, seed, rows, budget_s, max_mcs=200):
@@ -249,23 +262,37 @@ def main():
 
     w = HEADLINE
     K, Wm = args.steps, args.warmup
+    # The sweep runs as temporally blocked passes of DEPTH MCS each (all six
+    # half-steps of three MCS in one sweep over the state, BAND-row bands per
+    # workgroup), an even number of passes per call; the MCS left over run as
+    # two half-step launches each.  Both kinds of launch read the packed state
+    # once and write it once: X*Y/4 bytes each way.
+    DEPTH, BAND = 3, 64
+    n_pass = (K // DEPTH) & ~1
+    n_fused = n_pass * DEPTH
     torch.cuda.synchronize()
-    ms = time_path(torch, P, w.X, w.Y, w.p, w.q, w.seed, K, Wm)
+    if 0 < n_fused < K:
+        ms, fused_ms = time_path(torch, P, w.X, w.Y, w.p, w.q, w.seed, K, Wm, split=n_fused,
+                                 blocking=(DEPTH, BAND))
+    else:
+        ms = time_path(torch, P, w.X, w.Y, w.p, w.q, w.seed, K, Wm, blocking=(DEPTH, BAND))
+        fused_ms = ms
     value = w.sites * K / (ms / 1e3)
-    # Pairs of MCS run as one fused pass each (both half-steps in one sweep);
-    # an odd K adds one MCS of two half-step launches.  Every launch of either
-    # kind reads the packed state once and writes it once: X*Y/4 bytes each
-    # way.
-    fused = K % 2 == 0
-    launches = K if fused else (K - 1) + 2
-    avg_ms = ms / launches
     alg_bytes = w.sites // 2
-    achieved = alg_bytes * launches / (ms / 1e3) / 1e9
+    if n_pass:
+        avg_ms = fused_ms / n_pass
+        kernel = f"mcs_block_kernel<8,1,{DEPTH},Mask,false>"
+        per_update = alg_bytes / (w.sites * DEPTH)
+    else:
+        avg_ms = ms / (2 * K)
+        kernel = "halfstep_kernel<64,8,Mask,false>"
+        per_update = alg_bytes / w.sites
+    achieved = alg_bytes / (avg_ms / 1e3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": _traffic(alg_bytes),
-                "kernel": "mcs_fused_kernel<8,Mask,false>" if fused else "halfstep_kernel<64,8,Mask,false>",
-                "alg_bytes_per_launch": alg_bytes, "alg_bytes_per_site_update": alg_bytes / w.sites * (1 if fused else 2),
-                "avg_launch_ms": round(avg_ms, 5)}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": _traffic(alg_bytes), "kernel": kernel,
+                "alg_bytes_per_launch": alg_bytes, "mcs_per_launch": DEPTH if n_pass else 0.5,
+                "alg_bytes_per_site_update": per_update, "avg_launch_ms": round(avg_ms, 5),
+                "launches_timed": n_pass if n_pass else 2 * K}
 
     out = {
         "metric": "site updates/s (bit-vectorized sweep) vs HBM roofline",

@@ -90,12 +90,13 @@ int sca_init(sca_ctx** out, int64_t X, int64_t Y, uint64_t seed, void* slopes_de
 /* Advances n_mcs >= 0 MCS with deposition probability p and removal
  * probability q (Eq. (2)); each MCS is the even then the odd half-step
  * (Sec. I-A), t grows by n_mcs.  Asynchronous.
- * For 8192 <= X <= 65536 pairs of MCS run as fused passes (both half-steps
- * of an MCS in one sweep over the state, out of place into the library's
- * second buffer and back), which halves the HBM traffic per MCS; the results
- * are bit-identical to the two-launch form, and S holds the state when the
- * enqueued work has run.  If the second buffer cannot be allocated the call
- * falls back to two launches per MCS. */
+ * For X >= 8192 groups of MCS run as fused passes (all half-steps of
+ * `depth` MCS in one sweep over the state, out of place into the library's
+ * second buffer and back; see sca_set_blocking), which divides the HBM
+ * traffic per MCS by about 2*depth; the results are bit-identical to the
+ * two-launch form, and S holds the state when the enqueued work has run.  If
+ * the second buffer cannot be allocated the call falls back to two launches
+ * per MCS. */
 int sca_step(sca_ctx* ctx, int64_t n_mcs, double p, double q);
 
 /* sca_step with flags (SCA_FORCE_PERSITE, SCA_STEP_GRAPH).  With
@@ -133,9 +134,13 @@ int sca_autocorr(sca_ctx* ctx, const void* snap_dev, int64_t out4[4], double* c_
 /* Current MCS count t and origin height h(0,0).  Synchronizes. */
 int sca_get_meta(sca_ctx* ctx, int64_t* t, int64_t* h0);
 
-/* Rows per wavefront in the fused pass (a power of two >= 4 that divides Y,
- * default 32), or 0 to disable fusion for this context. */
-int sca_set_fused_band(sca_ctx* ctx, int32_t band);
+/* Temporal blocking of sca_step: depth = MCS per fused pass (1..3), 0 = never
+ * fuse, -1 = automatic (for dyadic p and q 3 on bands of >= 32 rows, 2 on 16,
+ * 1 otherwise; none for the per-site path, which is ALU-bound); band = rows
+ * per workgroup (a power of two >= 4 and >= 2*depth that divides Y, with
+ * Y >= 2*band), 0 = automatic (the tallest of 64, 32, 16, 8 that leaves
+ * enough workgroups to fill the chip). */
+int sca_set_blocking(sca_ctx* ctx, int32_t depth, int32_t band);
 
 /* Sets the MCS counter (for resuming from a saved state; the caller restores
  * S and aux itself).  0 <= t < 2^32. */

@@ -66,7 +66,7 @@ _SIGNATURES = {
     "sca_autocorr": ([_vp, _vp, _i64p, _dblp], _int),
     "sca_get_meta": ([_vp, _i64p, _i64p], _int),
     "sca_set_time": ([_vp, _i64], _int),
-    "sca_set_fused_band": ([_vp, ctypes.c_int32], _int),
+    "sca_set_blocking": ([_vp, ctypes.c_int32, ctypes.c_int32], _int),
     "sca_debug_halfstep": ([_vp, _int, _vp, _vp], _int),
     "sca_debug_philox": ([_vp, _u32, _u32, _i64, _vp, _vp], _int),
     "sca_destroy": ([_vp], None),

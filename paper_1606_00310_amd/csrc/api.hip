@@ -31,8 +31,9 @@ struct sca_ctx {
     bool failed = false;
     int64_t* ws = nullptr;     // library-owned: rows[3Y], col[Y], res[8]
     hipStream_t capture = nullptr;  // private stream for hipGraph capture (created on first use)
-    uint64_t* alt = nullptr;        // library-owned second state for the fused MCS pass (first use)
-    int32_t band = 32;              // rows per wavefront in the fused pass; 0 = never fuse
+    uint64_t* alt = nullptr;        // library-owned second state for the fused passes (first use)
+    int32_t depth = -1;             // MCS per fused pass; -1 = automatic, 0 = never fuse
+    int32_t band = 0;               // rows per workgroup in a fused pass; 0 = automatic
 };
 
 namespace {
@@ -251,11 +252,25 @@ int sca_step_ex(sca_ctx* c, int64_t n_mcs, double p, double q, unsigned flags)
     }
     const sca::XiMode mode = persite ? sca::XiMode::PerSite : sca::XiMode::Mask;
     const int64_t t0 = c->t;
-    // Pairs of MCS run as fused passes S -> alt -> S (one HBM pass per MCS);
-    // an odd last MCS, or lattices the fused pass does not cover, run as two
-    // in-place half-step launches.  The caller's S holds the state after every
-    // call either way.
-    bool fuse = !(flags & SCA_NO_FUSE) && c->band > 0 && n_mcs >= 2 && sca::fused_supported(c->W, c->Y, c->band);
+    // Groups of `depth` MCS run as fused passes alternating S -> alt -> S (one
+    // HBM pass per group); the number of passes is kept even so that the
+    // caller's S holds the state after the call, and the remaining MCS run as
+    // two in-place half-step launches each.
+    // Automatic choice: a band per workgroup with enough workgroups to fill
+    // the chip and bands as tall as that allows; 3 MCS per pass on tall bands
+    // (the halo costs 4*depth rows per band), fewer on short ones.  The
+    // per-site path is ALU-bound and runs unfused.
+    const int64_t nw = c->W >= 512 ? 8 : (c->W >= 64 ? c->W / 64 : 1);
+    int32_t band = c->band;
+    if (band == 0) {
+        int64_t b = 64;
+        while (b > 8 && c->Y / b < 2048 / nw) b >>= 1;
+        band = (int32_t)b;
+    }
+    int32_t depth = c->depth;
+    if (depth < 0) depth = persite ? 0 : (band >= 32 ? 3 : (band >= 16 ? 2 : 1));
+    bool fuse = !(flags & SCA_NO_FUSE) && depth > 0 && n_mcs >= 2 * (int64_t)depth &&
+                sca::fused_supported(c->W, c->Y, band, depth);
     if (fuse && !c->alt) {
         if (hipMalloc(&c->alt, sizeof(uint64_t) * (size_t)(4 * c->Y * c->W)) != hipSuccess) {
             (void)hipGetLastError();
@@ -263,16 +278,16 @@ int sca_step_ex(sca_ctx* c, int64_t n_mcs, double p, double q, unsigned flags)
             fuse = false;  // not enough memory for the second state: unfused launches
         }
     }
-    const int64_t n_fused = fuse ? (n_mcs & ~(int64_t)1) : 0;
+    const int64_t n_pass = fuse ? ((n_mcs / depth) & ~(int64_t)1) : 0;
     auto enqueue = [&](hipStream_t st) -> hipError_t {
-        for (int64_t i = 0; i < n_fused; ++i) {
-            a.t = (uint32_t)(t0 + i);
+        for (int64_t i = 0; i < n_pass; ++i) {
+            a.t = (uint32_t)(t0 + i * depth);
             const bool fwd = (i & 1) == 0;
             const hipError_t e = sca::launch_mcs_fused(a, mode, has_q, fwd ? c->S : c->alt, fwd ? c->alt : c->S,
-                                                       c->band, st);
+                                                       band, depth, st);
             if (e != hipSuccess) return e;
         }
-        for (int64_t i = n_fused; i < n_mcs; ++i) {
+        for (int64_t i = n_pass * depth; i < n_mcs; ++i) {
             a.t = (uint32_t)(t0 + i);
             for (int parity = 0; parity < 2; ++parity) {
                 a.parity = parity;
@@ -393,9 +408,11 @@ int sca_get_meta(sca_ctx* c, int64_t* t, int64_t* h0)
     return SCA_OK;
 }
 
-int sca_set_fused_band(sca_ctx* c, int32_t band)
+int sca_set_blocking(sca_ctx* c, int32_t depth, int32_t band)
 {
-    if (!c || band < 0 || (band > 0 && (band < 4 || (band & (band - 1)) != 0))) return SCA_EINVAL;
+    if (!c || depth < -1 || depth > 3 || band < 0 || (band > 0 && (band < 4 || (band & (band - 1)) != 0)))
+        return SCA_EINVAL;
+    c->depth = depth;
     c->band = band;
     return SCA_OK;
 }

@@ -39,11 +39,11 @@ struct SweepArgs {
 // Launches one half-step; returns the launch status.
 hipError_t launch_halfstep(const SweepArgs& a, XiMode mode, bool has_q, hipStream_t stream);
 
-// One MCS (even then odd half-step) in one pass, reading src and writing dst
-// (both S[2][2][Y][W]); bands of `band` rows per wavefront.
-bool fused_supported(int32_t W, int64_t Y, int32_t band);
+// `depth` MCS (2*depth half-steps from MCS a.t on) in one pass, reading src
+// and writing dst (both S[2][2][Y][W]); one workgroup per band of `band` rows.
+bool fused_supported(int32_t W, int64_t Y, int32_t band, int32_t depth);
 hipError_t launch_mcs_fused(const SweepArgs& a, XiMode mode, bool has_q, const uint64_t* src, uint64_t* dst,
-                            int32_t band, hipStream_t stream);
+                            int32_t band, int32_t depth, hipStream_t stream);
 
 // Flat initial surface into S and h0 = 0.
 hipError_t launch_flat_init(uint64_t* S, int64_t Y, int32_t W, int32_t nb, int64_t* h0,

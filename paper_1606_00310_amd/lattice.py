@@ -95,9 +95,10 @@ class Lattice:
         L.check(L.lib().sca_get_meta(self._ctx, ctypes.byref(t), None), "sca_get_meta")
         return int(t.value)
 
-    def set_fused_band(self, band: int):
-        """Rows per wavefront of the fused MCS pass (0 disables fusion)."""
-        L.check(L.lib().sca_set_fused_band(self._ctx, int(band)), "sca_set_fused_band")
+    def set_blocking(self, depth: int = -1, band: int = 0):
+        """MCS per fused pass (1..3; 0 never fuses, -1 automatic) and rows per
+        workgroup band (0 automatic)."""
+        L.check(L.lib().sca_set_blocking(self._ctx, int(depth), int(band)), "sca_set_blocking")
 
     def set_time(self, t: int):
         L.check(L.lib().sca_set_time(self._ctx, int(t)), "sca_set_time")

@@ -1,5 +1,5 @@
-"""The fused MCS pass (both half-steps in one sweep, out of place) against
-the two-launch form and the oracle."""
+"""The temporally blocked passes (all half-steps of `depth` MCS in one sweep,
+out of place) against the two-launch form and the oracle."""
 import sys
 
 import numpy as np
@@ -29,13 +29,15 @@ PROBS = [(0.5, 0.0, False), (0.75, 0.25, False), (0.9375, 0.0, False), (1.0, 0.0
          (0.93, 0.07, False), (0.5, 0.5, True)]
 
 
-@pytest.mark.parametrize("X,Y", [(8192, 64), (16384, 128), (32768, 64), (65536, 64), (8192, 256)])
+@pytest.mark.parametrize("X,Y", [(8192, 64), (16384, 128), (32768, 64), (65536, 64), (8192, 256), (131072, 32)])
 @pytest.mark.parametrize("p,q,persite", PROBS)
-def test_fused_vs_oracle(orc, sca, X, Y, p, q, persite):
-    _say(f"[fused] X={X} Y={Y} p={p} q={q}")
+@pytest.mark.parametrize("depth", [1, 2, 3])
+def test_fused_vs_oracle(orc, sca, X, Y, p, q, persite, depth):
+    _say(f"[fused] X={X} Y={Y} p={p} q={q} depth={depth}")
     seed = 31 + X + Y
     n = 6
     lat = sca.Lattice(X, Y, seed=seed)
+    lat.set_blocking(depth, 8)
     lat.step(n, p, q, force_persite=persite)
     st = orc.flat(X, Y, track_heights=False)
     orc.run(st, n, p, q, seed=seed, force_persite=persite)
@@ -45,13 +47,13 @@ def test_fused_vs_oracle(orc, sca, X, Y, p, q, persite):
     assert lat.roughness()[:3] == orc.moments(st)[:3]
 
 
-@pytest.mark.parametrize("band", [4, 8, 16, 32, 64])
-@pytest.mark.parametrize("n", [1, 2, 3, 8, 11])
-def test_fused_equals_unfused(sca, band, n):
+@pytest.mark.parametrize("depth,band", [(1, 4), (1, 16), (1, 64), (2, 4), (2, 8), (2, 32), (3, 8), (3, 64)])
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 13])
+def test_fused_equals_unfused(sca, depth, band, n):
     X, Y = 16384, 256
     a = sca.Lattice(X, Y, seed=5)
     b = sca.Lattice(X, Y, seed=5)
-    a.set_fused_band(band)
+    a.set_blocking(depth, band)
     a.step(n, 0.9375, 0.0)
     a.step(n + 1, 0.75, 0.25)
     b.step(n, 0.9375, 0.0, fuse=False)
@@ -66,11 +68,12 @@ def test_fused_graph_and_disable(sca):
     b = sca.Lattice(X, Y, seed=9)
     c = sca.Lattice(X, Y, seed=9)
     a.step(10, 0.5, 0.0, graph=True)
-    b.set_fused_band(0)
+    b.set_blocking(0)
     b.step(10, 0.5, 0.0)
     c.step(10, 0.5, 0.0)
     torch.cuda.synchronize()
     assert torch.equal(a.slopes, b.slopes) and torch.equal(b.slopes, c.slopes)
     assert a.meta() == b.meta() == c.meta()
-    with pytest.raises(sca.ScaError):
-        a.set_fused_band(12)
+    for bad in [(1, 12), (4, 8), (-2, 0)]:
+        with pytest.raises(sca.ScaError):
+            a.set_blocking(*bad)
