@@ -27,7 +27,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-COUNTERS = os.path.join(ROOT, "profiles", "mcs_fused_65536x65536_p1_counters.json")
+COUNTERS = os.path.join(ROOT, "profiles", "mcs_block_65536x65536_p1_counters.json")
 SWEEP_SRC = [os.path.join(ROOT, "paper_1606_00310_amd", "csrc", f)
              for f in ("fused.hip", "halfstep.hpp", "philox.hpp", "sca_internal.hpp")]
 
@@ -267,7 +267,7 @@ def main():
     # workgroup), an even number of passes per call; the MCS left over run as
     # two half-step launches each.  Both kinds of launch read the packed state
     # once and write it once: X*Y/4 bytes each way.
-    DEPTH, BAND = 3, 64
+    DEPTH, BAND = 3, 128
     n_pass = (K // DEPTH) & ~1
     n_fused = n_pass * DEPTH
     torch.cuda.synchronize()

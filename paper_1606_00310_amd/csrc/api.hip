@@ -263,7 +263,7 @@ int sca_step_ex(sca_ctx* c, int64_t n_mcs, double p, double q, unsigned flags)
     const int64_t nw = c->W >= 512 ? 8 : (c->W >= 64 ? c->W / 64 : 1);
     int32_t band = c->band;
     if (band == 0) {
-        int64_t b = 64;
+        int64_t b = 128;
         while (b > 8 && c->Y / b < 2048 / nw) b >>= 1;
         band = (int32_t)b;
     }
@@ -410,7 +410,7 @@ int sca_get_meta(sca_ctx* c, int64_t* t, int64_t* h0)
 
 int sca_set_blocking(sca_ctx* c, int32_t depth, int32_t band)
 {
-    if (!c || depth < -1 || depth > 3 || band < 0 || (band > 0 && (band < 4 || (band & (band - 1)) != 0)))
+    if (!c || depth < -1 || depth > 4 || band < 0 || (band > 0 && (band < 4 || (band & (band - 1)) != 0)))
         return SCA_EINVAL;
     c->depth = depth;
     c->band = band;

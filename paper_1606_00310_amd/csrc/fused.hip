@@ -106,9 +106,17 @@ __global__ __launch_bounds__(NW * 64) void mcs_block_kernel(SweepArgs a, const u
         }
     }
 
+    // the row entering the window at each step is loaded one step ahead
+    uint64_t Nx[4][I];
+    load_row(Nx, s0 + H);
+
     int buf = 0;
     for (int64_t s = s0; s < y1; ++s, buf ^= 1) {
-        load_row(Wn[R - 1], s + H);
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int i = 0; i < I; ++i) Wn[R - 1][c][i] = Nx[c][i];
+        if (s + 1 < y1) load_row(Nx, s + 1 + H);
         // bit 0 of the next word for each slot: lanes 0..62 from the next lane
         uint32_t msb_all = 0;
 #pragma unroll
@@ -236,7 +244,7 @@ hipError_t launch_depth(const SweepArgs& a, XiMode mode, bool has_q, const uint6
 
 bool fused_supported(int32_t W, int64_t Y, int32_t band, int32_t depth)
 {
-    return (W == 64 || W == 128 || W == 256 || W == 512 || W == 1024) && depth >= 1 && depth <= 3 && band >= 4 &&
+    return (W == 64 || W == 128 || W == 256 || W == 512 || W == 1024) && depth >= 1 && depth <= 4 && band >= 4 &&
            (band & (band - 1)) == 0 && (Y % band) == 0 && Y >= 2 * band && band >= 2 * depth;
 }
 
@@ -247,7 +255,8 @@ hipError_t launch_mcs_fused(const SweepArgs& a, XiMode mode, bool has_q, const u
     switch (depth) {
     case 1: return launch_depth<1>(a, mode, has_q, src, dst, band, stream);
     case 2: return launch_depth<2>(a, mode, has_q, src, dst, band, stream);
-    default: return launch_depth<3>(a, mode, has_q, src, dst, band, stream);
+    case 3: return launch_depth<3>(a, mode, has_q, src, dst, band, stream);
+    default: return launch_depth<4>(a, mode, has_q, src, dst, band, stream);
     }
 }
 

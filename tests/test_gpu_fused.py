@@ -31,7 +31,7 @@ PROBS = [(0.5, 0.0, False), (0.75, 0.25, False), (0.9375, 0.0, False), (1.0, 0.0
 
 @pytest.mark.parametrize("X,Y", [(8192, 64), (16384, 128), (32768, 64), (65536, 64), (8192, 256), (131072, 32)])
 @pytest.mark.parametrize("p,q,persite", PROBS)
-@pytest.mark.parametrize("depth", [1, 2, 3])
+@pytest.mark.parametrize("depth", [1, 2, 3, 4])
 def test_fused_vs_oracle(orc, sca, X, Y, p, q, persite, depth):
     _say(f"[fused] X={X} Y={Y} p={p} q={q} depth={depth}")
     seed = 31 + X + Y
@@ -47,7 +47,8 @@ def test_fused_vs_oracle(orc, sca, X, Y, p, q, persite, depth):
     assert lat.roughness()[:3] == orc.moments(st)[:3]
 
 
-@pytest.mark.parametrize("depth,band", [(1, 4), (1, 16), (1, 64), (2, 4), (2, 8), (2, 32), (3, 8), (3, 64)])
+@pytest.mark.parametrize("depth,band", [(1, 4), (1, 16), (1, 64), (2, 4), (2, 8), (2, 32), (3, 8), (3, 64), (4, 8),
+                                        (4, 128)])
 @pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 13])
 def test_fused_equals_unfused(sca, depth, band, n):
     X, Y = 16384, 256
@@ -74,6 +75,6 @@ def test_fused_graph_and_disable(sca):
     torch.cuda.synchronize()
     assert torch.equal(a.slopes, b.slopes) and torch.equal(b.slopes, c.slopes)
     assert a.meta() == b.meta() == c.meta()
-    for bad in [(1, 12), (4, 8), (-2, 0)]:
+    for bad in [(1, 12), (5, 8), (-2, 0)]:
         with pytest.raises(sca.ScaError):
             a.set_blocking(*bad)
