@@ -195,6 +195,7 @@ typedef struct sca_batch_config {
                               state (X >= 128; 4*Y*8 bytes for X < 128) run
                               from LDS; 0 = never; at most 65536 */
     int32_t order;         /* 0: longest remaining work first, 1: slot order */
+    int32_t words_per_lane;/* word tile: 64-site words per lane in a row, 1 or 2 */
 } sca_batch_config;
 
 typedef struct sca_slot_info {

@@ -542,7 +542,7 @@ bool valid_cfg(const sca_batch_config& c)
 {
     return (c.block_threads == 256 || c.block_threads == 512 || c.block_threads == 1024) && c.blocks_per_cu >= 1 &&
            c.blocks_per_cu <= 8 && c.lds_bytes >= 0 && c.lds_bytes <= 65536 && (c.lds_bytes % 8) == 0 &&
-           (c.order == 0 || c.order == 1);
+           (c.order == 0 || c.order == 1) && (c.words_per_lane == 1 || c.words_per_lane == 2);
 }
 
 }  // namespace
@@ -558,7 +558,7 @@ struct sca_batch {
     std::vector<SlotHost> slots;
     std::vector<int32_t> free_slots;  // stack of free slot ids
     ArenaAllocator alloc;
-    sca_batch_config cfg{512, 2, 65536, 0};
+    sca_batch_config cfg{512, 2, 65536, 0, 1};
     // device (library-owned)
     sca::BatchDesc* d_desc = nullptr;
     int32_t* d_order = nullptr;
@@ -611,7 +611,9 @@ hipError_t capture_epoch_graph(sca_batch* b)
     sca::BatchLaunch L{b->d_desc, b->d_order, b->d_counters, b->d_counters + 1, b->cfg.lds_bytes};
     if (hipStreamBeginCapture(b->capture, hipStreamCaptureModeRelaxed) != hipSuccess) return hipErrorUnknown;
     hipError_t e1 = sca::launch_counter_reset(b->d_counters + 1, b->capture);
-    if (e1 == hipSuccess) e1 = sca::launch_ensemble(L, b->cfg.block_threads, b->num_cus * b->cfg.blocks_per_cu, b->capture);
+    if (e1 == hipSuccess)
+        e1 = sca::launch_ensemble(L, b->cfg.block_threads, b->cfg.words_per_lane, b->num_cus * b->cfg.blocks_per_cu,
+                                  b->capture);
     hipGraph_t graph = nullptr;
     const hipError_t e2 = hipStreamEndCapture(b->capture, &graph);
     if (e1 != hipSuccess || e2 != hipSuccess || !graph) {
@@ -679,7 +681,8 @@ int sca_batch_set_config(sca_batch* b, const sca_batch_config* cfg)
     if (!b || !cfg || !valid_cfg(*cfg)) return SCA_EINVAL;
     if (b->failed) return SCA_ESTATE;
     const bool same = cfg->block_threads == b->cfg.block_threads && cfg->blocks_per_cu == b->cfg.blocks_per_cu &&
-                      cfg->lds_bytes == b->cfg.lds_bytes && cfg->order == b->cfg.order;
+                      cfg->lds_bytes == b->cfg.lds_bytes && cfg->order == b->cfg.order &&
+                      cfg->words_per_lane == b->cfg.words_per_lane;
     if (same) return SCA_OK;
     DeviceGuard dg(b->device);
     if (!dg.ok) return bfail(b);

@@ -15,63 +15,68 @@
 // half-step every word is read and written by exactly one lane; the barrier
 // between half-steps (a workgroup-scope release/acquire) orders them.
 #include "halfstep.hpp"
+#include "sca_internal.hpp"
 
 namespace sca {
 namespace {
 
-template <int W, XiMode MODE, bool HASQ, int NWAVES>
+// Word tile: a row of W words is held by W/IW lanes with IW words each
+// (IW = 2 gives every lane two independent random-word chains; rows of one
+// word always use one lane).
+template <int W, XiMode MODE, bool HASQ, int NWAVES, int IW>
 __device__ __forceinline__ void all_rows(const SweepArgs& a, uint64_t* S, int wave, int lane)
 {
-    constexpr int G = W;               // one row per group of W lanes, one word per lane
+    constexpr int I = (W >= IW) ? IW : 1;
+    constexpr int G = W / I;
     constexpr int kRowsPerWave = 64 / G;
     for (int64_t rb = (int64_t)wave * kRowsPerWave; rb < a.Y; rb += (int64_t)NWAVES * kRowsPerWave)
-        halfstep_rows<G, 1, MODE, HASQ>(a, S, rb + lane / G, lane);
+        halfstep_rows<G, I, MODE, HASQ>(a, S, rb + lane / G, lane);
 }
 
-template <int W, int NWAVES>
+template <int W, int NWAVES, int IW>
 __device__ __forceinline__ void all_rows_mode(const SweepArgs& a, uint64_t* S, int mode, bool has_q, int wave,
                                               int lane)
 {
     if (mode == 0) {
-        if (has_q) all_rows<W, XiMode::Mask, true, NWAVES>(a, S, wave, lane);
-        else all_rows<W, XiMode::Mask, false, NWAVES>(a, S, wave, lane);
+        if (has_q) all_rows<W, XiMode::Mask, true, NWAVES, IW>(a, S, wave, lane);
+        else all_rows<W, XiMode::Mask, false, NWAVES, IW>(a, S, wave, lane);
     } else {
-        if (has_q) all_rows<W, XiMode::PerSite, true, NWAVES>(a, S, wave, lane);
-        else all_rows<W, XiMode::PerSite, false, NWAVES>(a, S, wave, lane);
+        if (has_q) all_rows<W, XiMode::PerSite, true, NWAVES, IW>(a, S, wave, lane);
+        else all_rows<W, XiMode::PerSite, false, NWAVES, IW>(a, S, wave, lane);
     }
 }
 
 // Half-step over a state in LDS (W <= 8: at most 64 KiB fits only such rows
 // of a lattice with X*Y <= 2^18).
-template <int NWAVES>
+template <int NWAVES, int IW>
 __device__ __forceinline__ void halfstep_lds(const SweepArgs& a, uint64_t* S, int mode, bool has_q, int wave,
                                              int lane)
 {
     switch (a.W) {
-    case 1: all_rows_mode<1, NWAVES>(a, S, mode, has_q, wave, lane); break;
-    case 2: all_rows_mode<2, NWAVES>(a, S, mode, has_q, wave, lane); break;
-    case 4: all_rows_mode<4, NWAVES>(a, S, mode, has_q, wave, lane); break;
-    default: all_rows_mode<8, NWAVES>(a, S, mode, has_q, wave, lane); break;
+    case 1: all_rows_mode<1, NWAVES, IW>(a, S, mode, has_q, wave, lane); break;
+    case 2: all_rows_mode<2, NWAVES, IW>(a, S, mode, has_q, wave, lane); break;
+    case 4: all_rows_mode<4, NWAVES, IW>(a, S, mode, has_q, wave, lane); break;
+    default: all_rows_mode<8, NWAVES, IW>(a, S, mode, has_q, wave, lane); break;
     }
 }
 
 // Half-step over a state in global memory (W <= 64).
-template <int NWAVES>
+template <int NWAVES, int IW>
 __device__ __forceinline__ void halfstep_global(const SweepArgs& a, uint64_t* S, int mode, bool has_q, int wave,
                                                 int lane)
 {
     switch (a.W) {
-    case 1: all_rows_mode<1, NWAVES>(a, S, mode, has_q, wave, lane); break;
-    case 2: all_rows_mode<2, NWAVES>(a, S, mode, has_q, wave, lane); break;
-    case 4: all_rows_mode<4, NWAVES>(a, S, mode, has_q, wave, lane); break;
-    case 8: all_rows_mode<8, NWAVES>(a, S, mode, has_q, wave, lane); break;
-    case 16: all_rows_mode<16, NWAVES>(a, S, mode, has_q, wave, lane); break;
-    case 32: all_rows_mode<32, NWAVES>(a, S, mode, has_q, wave, lane); break;
-    default: all_rows_mode<64, NWAVES>(a, S, mode, has_q, wave, lane); break;
+    case 1: all_rows_mode<1, NWAVES, IW>(a, S, mode, has_q, wave, lane); break;
+    case 2: all_rows_mode<2, NWAVES, IW>(a, S, mode, has_q, wave, lane); break;
+    case 4: all_rows_mode<4, NWAVES, IW>(a, S, mode, has_q, wave, lane); break;
+    case 8: all_rows_mode<8, NWAVES, IW>(a, S, mode, has_q, wave, lane); break;
+    case 16: all_rows_mode<16, NWAVES, IW>(a, S, mode, has_q, wave, lane); break;
+    case 32: all_rows_mode<32, NWAVES, IW>(a, S, mode, has_q, wave, lane); break;
+    default: all_rows_mode<64, NWAVES, IW>(a, S, mode, has_q, wave, lane); break;
     }
 }
 
-template <int BLOCK>
+template <int BLOCK, int IW>
 __global__ __launch_bounds__(BLOCK) void ensemble_kernel(BatchLaunch L)
 {
     constexpr int NWAVES = BLOCK / 64;
@@ -116,7 +121,7 @@ __global__ __launch_bounds__(BLOCK) void ensemble_kernel(BatchLaunch L)
                 a.t = d.t + m;
                 for (int par = 0; par < 2; ++par) {
                     a.parity = par;
-                    halfstep_lds<NWAVES>(a, lds, d.mode, has_q, wave, lane);
+                    halfstep_lds<NWAVES, IW>(a, lds, d.mode, has_q, wave, lane);
                     __syncthreads();
                 }
             }
@@ -126,7 +131,7 @@ __global__ __launch_bounds__(BLOCK) void ensemble_kernel(BatchLaunch L)
                 a.t = d.t + m;
                 for (int par = 0; par < 2; ++par) {
                     a.parity = par;
-                    halfstep_global<NWAVES>(a, d.S, d.mode, has_q, wave, lane);
+                    halfstep_global<NWAVES, IW>(a, d.S, d.mode, has_q, wave, lane);
                     __syncthreads();
                 }
             }
@@ -138,13 +143,17 @@ __global__ void counter_reset_kernel(int32_t* c) { *c = 0; }
 
 }  // namespace
 
-hipError_t launch_ensemble(const BatchLaunch& L, int block_threads, int grid, hipStream_t stream)
+hipError_t launch_ensemble(const BatchLaunch& L, int block_threads, int words_per_lane, int grid, hipStream_t stream)
 {
     const size_t lds = (size_t)L.lds_bytes;
-    switch (block_threads) {
-    case 256: hipLaunchKernelGGL(ensemble_kernel<256>, dim3(grid), dim3(256), lds, stream, L); break;
-    case 512: hipLaunchKernelGGL(ensemble_kernel<512>, dim3(grid), dim3(512), lds, stream, L); break;
-    case 1024: hipLaunchKernelGGL(ensemble_kernel<1024>, dim3(grid), dim3(1024), lds, stream, L); break;
+    const int key = block_threads * 4 + words_per_lane;
+    switch (key) {
+    case 256 * 4 + 1: hipLaunchKernelGGL((ensemble_kernel<256, 1>), dim3(grid), dim3(256), lds, stream, L); break;
+    case 512 * 4 + 1: hipLaunchKernelGGL((ensemble_kernel<512, 1>), dim3(grid), dim3(512), lds, stream, L); break;
+    case 1024 * 4 + 1: hipLaunchKernelGGL((ensemble_kernel<1024, 1>), dim3(grid), dim3(1024), lds, stream, L); break;
+    case 256 * 4 + 2: hipLaunchKernelGGL((ensemble_kernel<256, 2>), dim3(grid), dim3(256), lds, stream, L); break;
+    case 512 * 4 + 2: hipLaunchKernelGGL((ensemble_kernel<512, 2>), dim3(grid), dim3(512), lds, stream, L); break;
+    case 1024 * 4 + 2: hipLaunchKernelGGL((ensemble_kernel<1024, 2>), dim3(grid), dim3(1024), lds, stream, L); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

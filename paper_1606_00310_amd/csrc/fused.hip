@@ -24,6 +24,7 @@
 // beyond their edges, so a pass reads `src` and writes `dst` (out of place);
 // every row of dst is written by exactly one band.
 #include "halfstep.hpp"
+#include "sca_internal.hpp"
 
 namespace sca {
 namespace {

@@ -29,7 +29,7 @@
 #pragma once
 
 #include "philox.hpp"
-#include "sca_internal.hpp"
+#include "sweep_args.hpp"
 
 namespace sca {
 

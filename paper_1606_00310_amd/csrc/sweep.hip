@@ -10,6 +10,7 @@
 // the first word separately, Sec. II-B) is a rotation of packed bits inside
 // the wave.  The arithmetic of a row group lives in halfstep.hpp.
 #include "halfstep.hpp"
+#include "sca_internal.hpp"
 
 namespace sca {
 namespace {

@@ -57,15 +57,17 @@ def solo_states(sca):
 
 
 CONFIGS = [
-    dict(block_threads=512, blocks_per_cu=2, lds_bytes=65536, order=0),
-    dict(block_threads=256, blocks_per_cu=4, lds_bytes=65536, order=1),
-    dict(block_threads=1024, blocks_per_cu=1, lds_bytes=0, order=0),
-    dict(block_threads=512, blocks_per_cu=1, lds_bytes=16384, order=1),
-    dict(block_threads=256, blocks_per_cu=8, lds_bytes=4096, order=0),
+    dict(block_threads=512, blocks_per_cu=2, lds_bytes=65536, order=0, words_per_lane=1),
+    dict(block_threads=256, blocks_per_cu=4, lds_bytes=65536, order=1, words_per_lane=2),
+    dict(block_threads=1024, blocks_per_cu=1, lds_bytes=0, order=0, words_per_lane=1),
+    dict(block_threads=1024, blocks_per_cu=1, lds_bytes=0, order=0, words_per_lane=2),
+    dict(block_threads=512, blocks_per_cu=1, lds_bytes=16384, order=1, words_per_lane=2),
+    dict(block_threads=256, blocks_per_cu=8, lds_bytes=4096, order=0, words_per_lane=1),
 ]
 
 
-@pytest.mark.parametrize("cfg", CONFIGS, ids=lambda c: "b{block_threads}-c{blocks_per_cu}-l{lds_bytes}-o{order}".format(**c))
+@pytest.mark.parametrize("cfg", CONFIGS,
+                         ids=lambda c: "b{block_threads}-c{blocks_per_cu}-l{lds_bytes}-o{order}-w{words_per_lane}".format(**c))
 @pytest.mark.parametrize("epoch", [5, 1000])
 def test_batch_equals_solo(sca, solo_states, cfg, epoch):
     from paper_1606_00310_amd.batch import Batch, state_bytes
