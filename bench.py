@@ -27,7 +27,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock: 32-bit VALU lane instructions/s
 COUNTERS = os.path.join(ROOT, "profiles", "mcs_block_65536x65536_p1_counters.json")
+VALU_COUNTERS = os.path.join(ROOT, "profiles", "valu_random_paths_counters.json")
 SWEEP_SRC = [os.path.join(ROOT, "paper_1606_00310_amd", "csrc", f)
              for f in ("fused.hip", "halfstep.hpp", "philox.hpp", "sweep_args.hpp")]
 
@@ -60,6 +62,20 @@ def _traffic(bytes_per_launch_alg):
     if c.get("sweep_sha256") != _sha(SWEEP_SRC):
         return None
     return c.get("hbm_bytes_per_launch")
+
+
+def _valu_per_update(tag):
+    """VALU lane instructions per site update that rocprofv3 counted for the
+    path's kernel, if the kernel sources are unchanged since."""
+    try:
+        with open(VALU_COUNTERS) as f:
+            c = json.load(f)[tag]
+    except (OSError, ValueError, KeyError):
+        return None
+    files = [os.path.join(ROOT, s) for s in c["sources"]]
+    if c.get("sources_sha256") != _sha(files):
+        return None
+    return c["valu_lane_instructions_per_site_update"]
 
 
 def time_path(torch, P, X, Y, p, q, seed, steps, warmup, force_persite=False, split=None, blocking=None):
@@ -232,6 +248,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched ensemble and serving runs")
     ap.add_argument("--ensemble-only", action="store_true", help="only the batched ensemble (for profiling)")
+    ap.add_argument("--only", choices=["random", "persite", "wide"],
+                    help="time one secondary path for --steps MCS and print it (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (torch copy_) three times, the known-size "
                          "reference for HBM byte counters")
@@ -255,6 +273,15 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         torch.cuda.empty_cache()
+
+    if args.only:
+        from paper_1606_00310_amd.inputs import HEADLINE_RANDOM, PERSITE, WIDE
+
+        wk = {"random": HEADLINE_RANDOM, "persite": PERSITE, "wide": WIDE}[args.only]
+        pms = time_path(torch, P, wk.X, wk.Y, wk.p, wk.q, wk.seed, args.steps, args.warmup)
+        print(json.dumps({"path": wk.name, "steps": args.steps, "ms": pms,
+                          "value": wk.sites * args.steps / (pms / 1e3)}), flush=True)
+        return
 
     if args.ensemble_only:
         print(json.dumps({"ensemble": bench_ensemble(torch, P, serving=False, solo=False)}), flush=True)
@@ -311,6 +338,18 @@ def main():
             rate = wk.sites * steps / (pms / 1e3)
             paths[wk.name] = {"value": rate, "unit": "site updates/s", "steps": steps,
                               "hbm_frac_1B_per_update": round(rate / (HBM_PEAK_GBS * 1e9), 4)}
+        # The random-word paths are bound by the VALU (Philox4x32-10): priced
+        # against 256 CUs x 64 lanes x 2.4 GHz of 32-bit VALU issue with the
+        # VALU instructions per site update that rocprofv3's SQ_INSTS_VALU
+        # counted for the same kernel build (profiles/valu_random_paths_*).
+        for tag, wk in (("persite", PERSITE), ("random", HEADLINE_RANDOM)):
+            per_update = _valu_per_update(tag)
+            pv = paths[wk.name]
+            pv["roofline"] = None if per_update is None else {
+                "bound": "alu", "achieved": pv["value"] * per_update, "peak": VALU_LANE_OPS,
+                "unit": "VALU lane instructions/s", "frac": round(pv["value"] * per_update / VALU_LANE_OPS, 4),
+                "valu_lane_instructions_per_site_update": per_update}
+        paths[PERSITE.name]["philox_only_blocks_per_s"] = P.philox_rate()
         out["paths"] = paths
 
     if not args.no_ensemble:

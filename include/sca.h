@@ -158,6 +158,12 @@ int sca_debug_halfstep(sca_ctx* ctx, int parity, const uint64_t* xi_p_dev,
 int sca_debug_philox(const uint32_t* ctr_dev, uint32_t k0, uint32_t k1, int64_t n,
                      uint32_t* out_dev, void* hip_stream);
 
+/* Diagnostic: `threads` threads (a multiple of 256) each evaluate `calls`
+ * Philox4x32-10 blocks and fold them into one word (stored into
+ * sink_dev[0..255] only if it happens to equal the key), to measure the
+ * generator's throughput on this device.  Asynchronous on hip_stream. */
+int sca_debug_philox_rate(int64_t threads, int32_t calls, uint32_t* sink_dev, void* hip_stream);
+
 /* Frees the context and its workspace (after synchronizing its stream).
  * Never frees caller buffers.  NULL is ignored. */
 void sca_destroy(sca_ctx* ctx);

@@ -69,6 +69,7 @@ _SIGNATURES = {
     "sca_set_blocking": ([_vp, ctypes.c_int32, ctypes.c_int32], _int),
     "sca_debug_halfstep": ([_vp, _int, _vp, _vp], _int),
     "sca_debug_philox": ([_vp, _u32, _u32, _i64, _vp, _vp], _int),
+    "sca_debug_philox_rate": ([_i64, ctypes.c_int32, _vp, _vp], _int),
     "sca_destroy": ([_vp], None),
     "sca_batch_state_bytes": ([_i64, _i64], ctypes.c_size_t),
     "sca_batch_create": ([ctypes.POINTER(_vp), ctypes.c_int32, _vp, ctypes.c_size_t, _vp], _int),

@@ -336,6 +336,15 @@ int sca_debug_philox(const uint32_t* ctr_dev, uint32_t k0, uint32_t k1, int64_t 
     return SCA_OK;
 }
 
+int sca_debug_philox_rate(int64_t threads, int32_t calls, uint32_t* sink_dev, void* hip_stream)
+{
+    if (threads <= 0 || (threads % 256) != 0 || threads > ((int64_t)1 << 31) || calls <= 0 || !sink_dev)
+        return SCA_EINVAL;
+    if (sca::launch_philox_rate(threads, calls, sink_dev, static_cast<hipStream_t>(hip_stream)) != hipSuccess)
+        return SCA_EDEVICE;
+    return SCA_OK;
+}
+
 int sca_roughness(sca_ctx* c, int64_t out3[3], double* w2)
 {
     if (!c || !out3) return SCA_EINVAL;

@@ -69,6 +69,8 @@ struct BatchLaunch {
 hipError_t launch_ensemble(const BatchLaunch& L, int block_threads, int words_per_lane, int grid, hipStream_t stream);
 hipError_t launch_counter_reset(int32_t* counter, hipStream_t stream);
 
+hipError_t launch_philox_rate(int64_t threads, int32_t calls, uint32_t* sink, hipStream_t stream);
+
 hipError_t launch_philox_test(const uint32_t* ctr, uint32_t k0, uint32_t k1, int64_t n,
                               uint32_t* out, hipStream_t stream);
 

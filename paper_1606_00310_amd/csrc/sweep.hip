@@ -59,7 +59,29 @@ __global__ void philox_test_kernel(const uint32_t* ctr, uint32_t k0, uint32_t k1
     out[4 * i + 3] = o.v3;
 }
 
+// Philox throughput: every thread evaluates `calls` blocks and folds them into
+// one word that is stored only in the (practically impossible) case that it
+// equals the key, so the work cannot be dropped.
+__global__ __launch_bounds__(256) void philox_rate_kernel(uint32_t k0, uint32_t k1, int32_t calls, uint32_t* sink)
+{
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t acc = 0;
+    for (int32_t j = 0; j < calls; ++j) {
+        const u32x4 o = philox4x32_10(g, (uint32_t)j, 0u, 0u, k0, k1);
+        acc ^= o.v0 ^ o.v1 ^ o.v2 ^ o.v3;
+    }
+    if (acc == k0) sink[g & 255u] = acc;
+}
+
 }  // namespace
+
+hipError_t launch_philox_rate(int64_t threads, int32_t calls, uint32_t* sink, hipStream_t stream)
+{
+    if (threads <= 0 || calls <= 0 || (threads % 256) != 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(philox_rate_kernel, dim3((unsigned)(threads / 256)), dim3(256), 0, stream, 0x9E3779B9u,
+                       0x243F6A88u, calls, sink);
+    return hipGetLastError();
+}
 
 hipError_t launch_halfstep(const SweepArgs& a, XiMode mode, bool has_q, hipStream_t stream)
 {

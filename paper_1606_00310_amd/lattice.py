@@ -123,3 +123,17 @@ def debug_philox(ctr: torch.Tensor, key0: int, key1: int) -> torch.Tensor:
     L.check(L.lib().sca_debug_philox(ctr.data_ptr(), key0 & 0xFFFFFFFF, key1 & 0xFFFFFFFF, n, out.data_ptr(),
                                      torch.cuda.current_stream(ctr.device).cuda_stream), "sca_debug_philox")
     return out
+
+
+def philox_rate(threads: int = 1 << 20, calls: int = 256, device="cuda") -> float:
+    """Philox4x32-10 blocks per second on this device (diagnostic kernel)."""
+    sink = torch.zeros(256, dtype=torch.int32, device=device)
+    stream = torch.cuda.current_stream(sink.device)
+    L.check(L.lib().sca_debug_philox_rate(threads, calls, sink.data_ptr(), stream.cuda_stream), "philox_rate")
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    L.check(L.lib().sca_debug_philox_rate(threads, calls, sink.data_ptr(), stream.cuda_stream), "philox_rate")
+    end.record(stream)
+    end.synchronize()
+    return threads * calls / (start.elapsed_time(end) / 1e3)
