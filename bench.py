@@ -308,7 +308,7 @@ def main():
     alg_bytes = w.sites // 2
     if n_pass:
         avg_ms = fused_ms / n_pass
-        kernel = f"mcs_block_kernel<8,1,{DEPTH},Mask,false>"
+        kernel = f"mcs_block_kernel<8,1,{DEPTH},Fixed,false>"
         per_update = alg_bytes / (w.sites * DEPTH)
     else:
         avg_ms = ms / (2 * K)

@@ -23,11 +23,71 @@
 // recomputations identical to the neighbouring bands' updates.  Bands read
 // beyond their edges, so a pass reads `src` and writes `dst` (out of place);
 // every row of dst is written by exactly one band.
+#include <utility>
+
 #include "halfstep.hpp"
 #include "sca_internal.hpp"
 
 namespace sca {
 namespace {
+
+// Calls f(integral_constant<u>, s + u) for u = 0 .. sizeof...(U)-1.
+template <class F, int... U>
+__device__ __forceinline__ void unrolled_steps(F& f, int s, std::integer_sequence<int, U...>)
+{
+    (f(std::integral_constant<int, U>{}, s + U), ...);
+}
+
+// Lane i receives v from lane i+1; lane 63 keeps `edge` (DPP wavefront shift).
+__device__ __forceinline__ uint32_t from_next_lane_or(uint32_t v, uint32_t edge)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)v, 0x130 /* wave_shl:1 */, 0xf, 0xf, false);
+}
+
+// Lane i receives v from lane i-1; lane 0 receives 0.
+__device__ __forceinline__ uint32_t from_prev_lane_or_zero(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138 /* wave_shr:1 */, 0xf, 0xf, true);
+}
+
+__device__ __forceinline__ uint64_t join(uint32_t lo, uint32_t hi) { return (uint64_t)lo | ((uint64_t)hi << 32); }
+
+// One half-step of one window row.  A, B: on-site x- and y- slopes; C: y+
+// slopes (the next row's other-sublattice y- words); D: x+ slopes (this row's
+// other-sublattice x- words).  SH: the row's x+ neighbours sit one site
+// further (bit k+1, across the word edge).  nbits: lane 63's next-word bits,
+// slot i in bit i.  In shifted rows the top mask bits are or-ed into msb_acc
+// at bit `at` + i, and lane 0's incoming carry is left for the caller.
+template <bool SH, int G, int I, XiMode MODE, bool HASQ>
+__device__ __forceinline__ void window_halfstep(const SweepArgs& ah, int rr, int gl, uint64_t (&A)[I],
+                                                uint64_t (&B)[I], uint64_t (&C)[I], uint64_t (&D)[I],
+                                                uint32_t nbits, uint32_t& msb_acc, int at, uint64_t& mp0,
+                                                uint64_t& mq0)
+{
+    uint64_t XP[I], M[I];
+#pragma unroll
+    for (int i = 0; i < I; ++i) {
+        if constexpr (SH) {
+            const uint32_t lo = (uint32_t)D[i], hi = (uint32_t)(D[i] >> 32);
+            const uint32_t nl = from_next_lane_or(lo, nbits >> i);  // bit 0: the next word's bit 0
+            XP[i] = join(__builtin_amdgcn_alignbit(hi, lo, 1u), __builtin_amdgcn_alignbit(nl, hi, 1u));
+        } else {
+            XP[i] = D[i];
+        }
+    }
+    row_masks<G, I, MODE, HASQ>(ah, rr, gl, A, B, C, XP, M, mp0, mq0);
+#pragma unroll
+    for (int i = 0; i < I; ++i) {
+        if constexpr (SH) {
+            const uint32_t lo = (uint32_t)M[i], hi = (uint32_t)(M[i] >> 32);
+            const uint32_t ph = from_prev_lane_or_zero(hi);        // bit 31: the previous word's top bit
+            D[i] ^= join(__builtin_amdgcn_alignbit(lo, ph, 31u), __builtin_amdgcn_alignbit(hi, lo, 31u));
+            msb_acc |= (hi >> 31) << (at + i);
+        } else {
+            D[i] ^= M[i];
+        }
+    }
+}
 
 template <int NW, int I, int K, XiMode MODE, bool HASQ>
 __global__ __launch_bounds__(NW * 64) void mcs_block_kernel(SweepArgs a, const uint64_t* src, uint64_t* dst,
@@ -35,37 +95,46 @@ __global__ __launch_bounds__(NW * 64) void mcs_block_kernel(SweepArgs a, const u
 {
     constexpr int H = 2 * K;      // half-steps per pass
     constexpr int R = 2 * K + 1;  // window rows
+    constexpr int NS = R + 1;     // register slots: the window and the row in flight
+    // Without per-site compares the step body is small: the sweep is unrolled
+    // NS steps deep so that the window rotates through the slots instead of
+    // being moved down one slot per step, and each unrolled step knows at
+    // compile time whether its rows are shifted.
+    constexpr bool ROT = MODE == XiMode::Fixed;
     static_assert(H * I <= 32, "exchange bits per lane");
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    const int64_t y0 = (int64_t)blockIdx.x * band, y1 = y0 + band;
-    const int64_t ymask = a.Y - 1;
+    const int y0 = (int)blockIdx.x * band, y1 = y0 + band;
+    const int ymask = a.Y - 1;
     const int64_t P = a.plane, W = a.W;
+    const uint32_t wo = (uint32_t)(wv * 64 + lane);  // slot 0's word in the row
+    // byte offset of slot i's word from the start of its row (32-bit, so the
+    // row base stays in scalar registers)
+    auto off = [&](int i) -> uint32_t { return (wo + (uint32_t)(i * 64 * NW)) * 8u; };
     __shared__ uint32_t xa[2][NW];  // lane 0: bit 0 of the x+ words of the next step's half-steps
     __shared__ uint32_t xb[2][NW];  // lane 63: top bits of this step's masks
 
-    // window row j holds row s+j: arrays 0 = x-(even), 1 = x-(odd), 2 = y-(even), 3 = y-(odd)
-    uint64_t Wn[R][4][I];
+    // slot arrays: 0 = x-(even), 1 = x-(odd), 2 = y-(even), 3 = y-(odd)
+    uint64_t Wn[NS][4][I];
     uint32_t nb0 = 0;  // lane 63: bit 0 of the next wave's first word, per (half-step, slot)
+    int buf = 0;
 
-    auto word = [&](int i) -> int64_t { return (int64_t)i * (64 * NW) + wv * 64 + lane; };
     // rows below y0-2K feed no half-step the band needs: not loaded
-    auto load_row = [&](uint64_t (&row)[4][I], int64_t r) {
-        const int64_t rr = r & ymask;
-        const bool need = r >= y0 - H;
+    auto load_row = [&](uint64_t (&row)[4][I], int r) {
+        const int rr = r & ymask;
+        if (r >= y0 - H) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
+            for (int c = 0; c < 4; ++c) {
+                const char* base = (const char*)(src + (c * P + rr * W));
 #pragma unroll
-            for (int i = 0; i < I; ++i) row[c][i] = need ? src[c * P + rr * W + word(i)] : 0ull;
-    };
-    // bit 0 of each half-step's x+ words for the step whose window is Wn
-    auto lsb_bits = [&]() -> uint32_t {
-        uint32_t v = 0;
+                for (int i = 0; i < I; ++i) row[c][i] = *(const uint64_t*)(base + off(i));
+            }
+        } else {
 #pragma unroll
-        for (int h = 0; h < H; ++h)
+            for (int c = 0; c < 4; ++c)
 #pragma unroll
-            for (int i = 0; i < I; ++i) v |= (uint32_t)(Wn[H - 1 - h][1 - (h & 1)][i] & 1ull) << (h * I + i);
-        return v;
+                for (int i = 0; i < I; ++i) row[c][i] = 0ull;
+        }
     };
     // from the next wave's lane 0 (the last wave continues in slot i+1 of wave 0)
     auto take_next = [&](uint32_t v) -> uint32_t {
@@ -92,84 +161,62 @@ __global__ __launch_bounds__(NW * 64) void mcs_block_kernel(SweepArgs a, const u
     // half-step of row y0-1 writes y-slopes of row y0, and each earlier
     // half-step widens the cone by one row), so half-step 0 starts on row
     // y0-2K, which the skewed sweep reaches at step y0-4K+1.
-    const int64_t s0 = y0 - 2 * H + 1;
-    // prologue: window rows s0 .. s0+2K-1, and the next-word bits for the first step
-#pragma unroll
-    for (int j = 0; j < R - 1; ++j) load_row(Wn[j], s0 + j);
-    {
-        const uint32_t v = lsb_bits();
-        if (NW > 1) {
-            if (lane == 0) xa[1][wv] = v;
-            __syncthreads();
-            if (lane == 63) nb0 = take_next(xa[1][(wv + 1) % NW]);
-        } else {
-            nb0 = take_next((uint32_t)__shfl((int)v, 0));
-        }
-    }
+    const int s0 = y0 - 2 * H + 1;
 
-    // the row entering the window at each step is loaded one step ahead
-    uint64_t Nx[4][I];
-    load_row(Nx, s0 + H);
-
-    int buf = 0;
-    for (int64_t s = s0; s < y1; ++s, buf ^= 1) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-#pragma unroll
-            for (int i = 0; i < I; ++i) Wn[R - 1][c][i] = Nx[c][i];
-        if (s + 1 < y1) load_row(Nx, s + 1 + H);
-        // bit 0 of the next word for each slot: lanes 0..62 from the next lane
+    // Step s (u = (s - s0) mod NS when the slots rotate, else 0) holds row
+    // s+j in slot (u+j) mod NS: rows s .. s+2K form the window, and row
+    // s+2K+1 is loaded into the slot freed by row s-1, one step ahead of use.
+    // Half-step h works on row s+2K-1-h with parity h&1, so all half-steps of
+    // a step have the same row alignment: shifted iff s+2K-1 is odd, i.e. iff
+    // s is even.  With the band a multiple of two, s0 is odd, so in the
+    // rotating sweep step u is shifted iff u is odd.
+    auto step = [&](auto U, int s) {
+        constexpr int u = decltype(U)::value;
+        if (s >= y1) return;
+        auto sl = [](int j) { return (u + j) % NS; };
+        if (s + 1 < y1) load_row(Wn[sl(H + 1)], s + 1 + H);
+        const bool shifted = ROT ? (u & 1) != 0 : (s & 1) == 0;
         uint32_t msb_all = 0;
 #pragma unroll
         for (int h = 0; h < H; ++h) {
             const int j = H - 1 - h;          // window row of half-step h
-            const int64_t r = s + j;          // its row
+            const int r = s + j;              // its row
             const int par = h & 1;
             if (r < y0 - H + h) continue;     // not needed by the band's rows (and inputs not loaded)
-            const int64_t rr = r & ymask;
-            const bool shifted = ((par ^ (int)(rr & 1)) != 0);
-            uint64_t(&D)[I] = Wn[j][1 - par];
-            uint64_t XP[I], M[I], mp0 = 0, mq0 = 0;
-            uint32_t lsb = 0;
-#pragma unroll
-            for (int i = 0; i < I; ++i) lsb |= (uint32_t)(D[i] & 1ull) << i;
-            uint32_t nxt = (uint32_t)__shfl((int)lsb, (lane + 1) & 63);
-            if (lane == 63) nxt = (nb0 >> (h * I)) & ((1u << I) - 1u);
-#pragma unroll
-            for (int i = 0; i < I; ++i)
-                XP[i] = shifted ? ((D[i] >> 1) | ((uint64_t)((nxt >> i) & 1u) << 63)) : D[i];
+            const int rr = r & ymask;
             SweepArgs ah = a;
             ah.parity = par;
             ah.t = a.t + (uint32_t)(h >> 1);
+            uint64_t mp0 = 0, mq0 = 0;
+            const uint32_t nbits = nb0 >> (h * I);
             // row_masks indexes words as i*G + gl with G = 64*NW
-            row_masks<64 * NW, I, MODE, HASQ>(ah, rr, wv * 64 + lane, Wn[j][par], Wn[j][2 + par],
-                                                Wn[j + 1][2 + (1 - par)], XP, M, mp0, mq0);
-            // x+ slopes: in-wave carries now, the first lane's carry after the exchange
-            uint32_t msb = 0;
-#pragma unroll
-            for (int i = 0; i < I; ++i) msb |= (uint32_t)(M[i] >> 63) << i;
-            const uint32_t prv = (uint32_t)__shfl((int)msb, (lane + 63) & 63);
-#pragma unroll
-            for (int i = 0; i < I; ++i) {
-                const uint64_t carry = (lane == 0) ? 0ull : (uint64_t)((prv >> i) & 1u);
-                D[i] ^= shifted ? ((M[i] << 1) | carry) : M[i];
-            }
-            msb_all |= msb << (h * I);
-            if (par == 0 && rr == 0 && r >= y0 && r < y1 && wv == 0 && lane == 0) {
+            if (ROT ? (u & 1) != 0 : shifted)
+                window_halfstep<true, 64 * NW, I, MODE, HASQ>(ah, rr, (int)wo, Wn[sl(j)][par], Wn[sl(j)][2 + par],
+                                                              Wn[sl(j + 1)][2 + (1 - par)], Wn[sl(j)][1 - par],
+                                                              nbits, msb_all, h * I, mp0, mq0);
+            else
+                window_halfstep<false, 64 * NW, I, MODE, HASQ>(ah, rr, (int)wo, Wn[sl(j)][par], Wn[sl(j)][2 + par],
+                                                               Wn[sl(j + 1)][2 + (1 - par)], Wn[sl(j)][1 - par],
+                                                               nbits, msb_all, h * I, mp0, mq0);
+            if (par == 0 && rr == 0 && r >= y0 && r < y1 && wo == 0) {
                 const int64_t dh = 2 * (int64_t)(mp0 & 1ull) - 2 * (int64_t)(mq0 & 1ull);
                 if (dh != 0) *a.h0 += dh;
             }
         }
-        // exchange: this step's top mask bits (for the first lanes' carries) and
-        // the next step's next-word bits; one barrier
+        // exchange: this step's top mask bits (for the first lanes' carries,
+        // shifted rows only) and the next step's next-word bits (needed only
+        // if the next step is shifted, i.e. this one is not); one barrier
         {
             // next step's window is rows s+1 .. s+2K+1; its half-step h x+ words
-            // are Wn[H - h][1 - (h & 1)] of the current window
+            // are in window row H-h of the current step
             uint32_t v = 0;
+            if (!shifted) {
 #pragma unroll
-            for (int h = 0; h < H; ++h)
+                for (int h = 0; h < H; ++h)
 #pragma unroll
-                for (int i = 0; i < I; ++i) v |= (uint32_t)(Wn[H - h][1 - (h & 1)][i] & 1ull) << (h * I + i);
+                    for (int i = 0; i < I; ++i)
+                        v |= (uint32_t)(Wn[sl(H - h)][1 - (h & 1)][i] & 1ull) << (h * I + i);
+            }
             uint32_t pm, nv;
             if (NW > 1) {
                 if (lane == 0) xa[buf][wv] = v;
@@ -177,37 +224,50 @@ __global__ __launch_bounds__(NW * 64) void mcs_block_kernel(SweepArgs a, const u
                 __syncthreads();
                 pm = (lane == 0) ? take_prev(xb[buf][(wv + NW - 1) % NW]) : 0u;
                 nv = (lane == 63) ? take_next(xa[buf][(wv + 1) % NW]) : 0u;
+                buf ^= 1;
             } else {
-                pm = take_prev((uint32_t)__shfl((int)msb_all, 63));
-                nv = take_next((uint32_t)__shfl((int)v, 0));
+                pm = take_prev((uint32_t)__builtin_amdgcn_readlane((int)msb_all, 63));
+                nv = take_next((uint32_t)__builtin_amdgcn_readlane((int)v, 0));
             }
-            if (lane == 0) {
+            if (shifted && lane == 0) {
 #pragma unroll
                 for (int h = 0; h < H; ++h) {
                     const int j = H - 1 - h;
                     const int par = h & 1;
-                    const bool shifted = ((par ^ (int)((s + j) & 1)) != 0);
-                    if (shifted) {
 #pragma unroll
-                        for (int i = 0; i < I; ++i) Wn[j][1 - par][i] ^= (uint64_t)((pm >> (h * I + i)) & 1u);
-                    }
+                    for (int i = 0; i < I; ++i) Wn[sl(j)][1 - par][i] ^= (uint64_t)((pm >> (h * I + i)) & 1u);
                 }
             }
             if (lane == 63) nb0 = nv;
         }
         if (s >= y0) {
-            const int64_t rr = s & ymask;
+            const int rr = s & ymask;
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
+            for (int c = 0; c < 4; ++c) {
+                char* base = (char*)(dst + (c * P + rr * W));
 #pragma unroll
-                for (int i = 0; i < I; ++i) dst[c * P + rr * W + word(i)] = Wn[0][c][i];
+                for (int i = 0; i < I; ++i) *(uint64_t*)(base + off(i)) = Wn[sl(0)][c][i];
+            }
         }
+    };
+
+    // prologue: rows s0 .. s0+2K, and the next-word bits for the first step
+    // (s0 is odd, so the first step is not shifted and needs none)
 #pragma unroll
-        for (int j = 0; j < R - 1; ++j)
+    for (int j = 0; j < R; ++j) load_row(Wn[j], s0 + j);
+
+    if constexpr (ROT) {
+        for (int s = s0; s < y1; s += NS) unrolled_steps(step, s, std::make_integer_sequence<int, NS>{});
+    } else {
+        for (int s = s0; s < y1; ++s) {
+            step(std::integral_constant<int, 0>{}, s);
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
+            for (int j = 0; j < NS - 1; ++j)
 #pragma unroll
-                for (int i = 0; i < I; ++i) Wn[j][c][i] = Wn[j + 1][c][i];
+                for (int c = 0; c < 4; ++c)
+#pragma unroll
+                    for (int i = 0; i < I; ++i) Wn[j][c][i] = Wn[j + 1][c][i];
+        }
     }
 }
 
@@ -217,7 +277,10 @@ hipError_t launch_block(const SweepArgs& a, XiMode mode, bool has_q, const uint6
 {
     const dim3 grid((unsigned)(a.Y / band));
     const dim3 block(NW * 64);
-    if (mode == XiMode::Mask) {
+    if (mode == XiMode::Mask && a.ndraw == 0) {
+        if (has_q) hipLaunchKernelGGL((mcs_block_kernel<NW, I, K, XiMode::Fixed, true>), grid, block, 0, stream, a, src, dst, band);
+        else hipLaunchKernelGGL((mcs_block_kernel<NW, I, K, XiMode::Fixed, false>), grid, block, 0, stream, a, src, dst, band);
+    } else if (mode == XiMode::Mask) {
         if (has_q) hipLaunchKernelGGL((mcs_block_kernel<NW, I, K, XiMode::Mask, true>), grid, block, 0, stream, a, src, dst, band);
         else hipLaunchKernelGGL((mcs_block_kernel<NW, I, K, XiMode::Mask, false>), grid, block, 0, stream, a, src, dst, band);
     } else {

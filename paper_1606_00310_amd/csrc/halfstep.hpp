@@ -78,6 +78,28 @@ __device__ __forceinline__ void persite_words(const SweepArgs& a, uint32_t g, bo
     xq = has_q ? (((uint64_t)lo_q | ((uint64_t)hi_q << 32)) | a.all_q) : 0;
 }
 
+// Any bitwise function of three words in one gfx950 v_bitop3_b32 per half:
+// bit (a<<2 | b<<1 | c) of T is the result for input bits a, b, c.
+template <unsigned T>
+__device__ __forceinline__ uint64_t bitop3(uint64_t a, uint64_t b, uint64_t c)
+{
+    const uint32_t lo = __builtin_amdgcn_bitop3_b32((uint32_t)a, (uint32_t)b, (uint32_t)c, T);
+    const uint32_t hi = __builtin_amdgcn_bitop3_b32((uint32_t)(a >> 32), (uint32_t)(b >> 32), (uint32_t)(c >> 32), T);
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+// Lane i of the wavefront receives v from lane (i+1) mod 64, resp. (i-1) mod
+// 64: DPP wavefront rotates, a VALU operation with no LDS round trip.
+__device__ __forceinline__ uint32_t from_next_lane(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x134 /* wave_rol:1 */, 0xf, 0xf, false);
+}
+
+__device__ __forceinline__ uint32_t from_prev_lane(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x13c /* wave_ror:1 */, 0xf, 0xf, false);
+}
+
 template <int N>
 __device__ __forceinline__ uint32_t rot_down(uint32_t v)  // bit i <- bit (i+1) mod N
 {
@@ -110,7 +132,8 @@ __device__ __forceinline__ void align_xplus(const uint64_t (&D)[I], bool shifted
 #pragma unroll
         for (int i = 0; i < I; ++i) lsb |= (uint32_t)(D[i] & 1ull) << i;
         uint32_t nxt = lsb;
-        if constexpr (G > 1) nxt = (uint32_t)__shfl((int)lsb, gbase | ((gl + 1) & (G - 1)));
+        if constexpr (G == 64) nxt = from_next_lane(lsb);
+        else if constexpr (G > 1) nxt = (uint32_t)__shfl((int)lsb, gbase | ((gl + 1) & (G - 1)));
         // The last lane of the group continues in slot i+1 of the first lane.
         if (gl == G - 1) nxt = rot_down<I>(nxt);
 #pragma unroll
@@ -134,7 +157,8 @@ __device__ __forceinline__ void apply_xplus(uint64_t (&D)[I], const uint64_t (&M
 #pragma unroll
         for (int i = 0; i < I; ++i) msb |= (uint32_t)(M[i] >> 63) << i;
         uint32_t prv = msb;
-        if constexpr (G > 1) prv = (uint32_t)__shfl((int)msb, gbase | ((gl - 1) & (G - 1)));
+        if constexpr (G == 64) prv = from_prev_lane(msb);
+        else if constexpr (G > 1) prv = (uint32_t)__shfl((int)msb, gbase | ((gl - 1) & (G - 1)));
         // The first lane of the group continues from slot i-1 of the last lane.
         if (gl == 0) prv = rot_up<I>(prv);
 #pragma unroll
@@ -160,12 +184,16 @@ __device__ __forceinline__ void row_masks(const SweepArgs& a, int64_t y, int gl,
             mask_words(a, g, HASQ, xip, xiq);
         } else if constexpr (MODE == XiMode::PerSite) {
             persite_words(a, g, HASQ, xip, xiq);
+        } else if constexpr (MODE == XiMode::Fixed) {
+            xip = a.all_p;
+            xiq = a.all_q;
         } else {
             xip = a.xi_p[g];
             xiq = a.xi_q[g];
         }
-        const uint64_t mp = xip & ~A[i] & ~B[i] & XP[i] & C[i];
-        const uint64_t mq = HASQ ? (xiq & A[i] & B[i] & ~XP[i] & ~C[i]) : 0ull;
+        const uint64_t mp = bitop3<0x80>(bitop3<0x02>(A[i], B[i], XP[i]), C[i], xip);  // xi & ~A & ~B & XP & C
+        const uint64_t mq = HASQ ? bitop3<0x20>(bitop3<0x40>(A[i], B[i], XP[i]), C[i], xiq)  // xi & A & B & ~XP & ~C
+                                 : 0ull;
         if (i == 0) { mp0 = mp; mq0 = mq; }
         M[i] = mp | mq;
         A[i] ^= M[i];

@@ -10,6 +10,7 @@ enum class XiMode : int {
     Mask = 0,     // dyadic p, q: and/or fold of n 64-bit draws (Sec. III)
     PerSite = 1,  // one 32-bit uniform per site against floor(r*2^32) (Sec. II-B)
     Inject = 2,   // read from caller arrays (test hook)
+    Fixed = 3,    // p, q in {0, 1}: xi is all ones or zero, no draws
 };
 
 // Everything a half-step launch needs; passed by value as the kernel argument.
