@@ -30,8 +30,6 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock: 32-bit VALU lane instructions/s
 COUNTERS = os.path.join(ROOT, "profiles", "mcs_block_65536x65536_p1_counters.json")
 VALU_COUNTERS = os.path.join(ROOT, "profiles", "valu_random_paths_counters.json")
-SWEEP_SRC = [os.path.join(ROOT, "paper_1606_00310_amd", "csrc", f)
-             for f in ("fused.hip", "halfstep.hpp", "philox.hpp", "sweep_args.hpp")]
 
 
 def _ensure_built():
@@ -52,14 +50,15 @@ def _sha(paths):
 
 
 def _traffic(bytes_per_launch_alg):
-    """Counter-measured HBM bytes per half-step launch, if the counters were
-    taken on the current kernel source."""
+    """Counter-measured HBM bytes per blocked-pass launch, if the counters were
+    taken on the current kernel sources."""
     try:
         with open(COUNTERS) as f:
             c = json.load(f)
     except (OSError, ValueError):
         return None
-    if c.get("sweep_sha256") != _sha(SWEEP_SRC):
+    files = [os.path.join(ROOT, s) for s in c.get("sources", [])]
+    if not files or c.get("sources_sha256") != _sha(files):
         return None
     return c.get("hbm_bytes_per_launch")
 
@@ -289,12 +288,12 @@ def main():
 
     w = HEADLINE
     K, Wm = args.steps, args.warmup
-    # The sweep runs as temporally blocked passes of DEPTH MCS each (all six
-    # half-steps of three MCS in one sweep over the state, BAND-row bands per
+    # The sweep runs as temporally blocked passes of DEPTH MCS each (all ten
+    # half-steps of five MCS in one sweep over the state, BAND-row bands per
     # workgroup), an even number of passes per call; the MCS left over run as
     # two half-step launches each.  Both kinds of launch read the packed state
     # once and write it once: X*Y/4 bytes each way.
-    DEPTH, BAND = 3, 128
+    DEPTH, BAND = 5, 128
     n_pass = (K // DEPTH) & ~1
     n_fused = n_pass * DEPTH
     torch.cuda.synchronize()

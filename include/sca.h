@@ -134,12 +134,17 @@ int sca_autocorr(sca_ctx* ctx, const void* snap_dev, int64_t out4[4], double* c_
 /* Current MCS count t and origin height h(0,0).  Synchronizes. */
 int sca_get_meta(sca_ctx* ctx, int64_t* t, int64_t* h0);
 
-/* Temporal blocking of sca_step: depth = MCS per fused pass (1..4), 0 = never
- * fuse, -1 = automatic (for dyadic p and q 3 on bands of >= 32 rows, 2 on 16,
- * 1 otherwise; none for the per-site path, which is ALU-bound); band = rows
- * per workgroup (a power of two >= 4 and >= 2*depth that divides Y, with
- * Y >= 2*band), 0 = automatic (the tallest of 128, 64, 32, 16, 8 that
- * leaves enough workgroups to fill the chip). */
+/* Temporal blocking of sca_step: depth = MCS per fused pass (1..8), 0 = never
+ * fuse, -1 = automatic; band = rows per workgroup (a power of two >= 4 and
+ * >= 2*depth that divides Y, with Y >= 2*band), 0 = automatic (the tallest of
+ * 128, 64, 32, 16, 8 that leaves enough workgroups to fill the chip).
+ * Passes run at most 8 MCS deep when p and q are both 0 or 1 (no random
+ * words; at most 5 for X = 2^17), and at most 4 deep otherwise: a larger
+ * depth is lowered to that limit when sca_step runs.  The automatic depth is
+ * 5 without random words and 3 with them on bands of >= 64 rows, 3 on 32-row
+ * bands, 2 on 16 and 1 on smaller ones; the per-site path (non-dyadic p or
+ * q), which is ALU-bound, is never fused.  Any setting gives bit-identical
+ * results. */
 int sca_set_blocking(sca_ctx* ctx, int32_t depth, int32_t band);
 
 /* Sets the MCS counter (for resuming from a saved state; the caller restores

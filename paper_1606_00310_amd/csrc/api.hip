@@ -257,9 +257,9 @@ int sca_step_ex(sca_ctx* c, int64_t n_mcs, double p, double q, unsigned flags)
     // caller's S holds the state after the call, and the remaining MCS run as
     // two in-place half-step launches each.
     // Automatic choice: a band per workgroup with enough workgroups to fill
-    // the chip and bands as tall as that allows; 3 MCS per pass on tall bands
-    // (the halo costs 4*depth rows per band), fewer on short ones.  The
-    // per-site path is ALU-bound and runs unfused.
+    // the chip and bands as tall as that allows; deep passes on tall bands
+    // (the halo costs 4*depth rows per band), shallower ones on short bands.
+    // The per-site path is ALU-bound and runs unfused.
     const int64_t nw = c->W >= 512 ? 8 : (c->W >= 64 ? c->W / 64 : 1);
     int32_t band = c->band;
     if (band == 0) {
@@ -267,10 +267,25 @@ int sca_step_ex(sca_ctx* c, int64_t n_mcs, double p, double q, unsigned flags)
         while (b > 8 && c->Y / b < 2048 / nw) b >>= 1;
         band = (int32_t)b;
     }
+    // Without random words (p, q in {0, 1}) a pass is bandwidth-bound and
+    // costs about the same at any depth whose window fits the registers of
+    // two workgroups per compute unit, which is 5 MCS; passes with draws are
+    // ALU-bound and do best at 3.
+    const bool draw_free = !persite && a.ndraw == 0;
+    const int32_t dmax = sca::max_fused_depth(c->W, draw_free);
     int32_t depth = c->depth;
-    if (depth < 0) depth = persite ? 0 : (band >= 32 ? 3 : (band >= 16 ? 2 : 1));
+    if (depth < 0) {
+        depth = persite ? 0
+                        : band >= 64 ? (draw_free ? 5 : 3)
+                        : band >= 32 ? 3
+                        : band >= 16 ? 2
+                                     : 1;
+    }
+    if (depth > dmax) {
+        depth = dmax;
+    }
     bool fuse = !(flags & SCA_NO_FUSE) && depth > 0 && n_mcs >= 2 * (int64_t)depth &&
-                sca::fused_supported(c->W, c->Y, band, depth);
+                sca::fused_supported(c->W, c->Y, band, depth, draw_free);
     if (fuse && !c->alt) {
         if (hipMalloc(&c->alt, sizeof(uint64_t) * (size_t)(4 * c->Y * c->W)) != hipSuccess) {
             (void)hipGetLastError();
@@ -419,7 +434,7 @@ int sca_get_meta(sca_ctx* c, int64_t* t, int64_t* h0)
 
 int sca_set_blocking(sca_ctx* c, int32_t depth, int32_t band)
 {
-    if (!c || depth < -1 || depth > 4 || band < 0 || (band > 0 && (band < 4 || (band & (band - 1)) != 0)))
+    if (!c || depth < -1 || depth > 8 || band < 0 || (band > 0 && (band < 4 || (band & (band - 1)) != 0)))
         return SCA_EINVAL;
     c->depth = depth;
     c->band = band;

@@ -1,326 +1,33 @@
-// fused.hip -- K Monte-Carlo steps (2K half-steps) in one pass over the lattice.
-//
-// Half-step h of row r reads only values that half-step h-1 produces in rows
-// r-1, r and r+1 (the checkerboard order of Sec. I-A: the x- and y- slopes of
-// row r and the y+ slopes of row r+1).  So one sweep down the rows can keep a
-// window of 2K+1 rows and, at each step s, apply half-step h to row
-// s+2K-1-h for h = 0..2K-1 (even half-steps at even h): every row of the
-// state is then loaded and stored once per K MCS instead of once per
-// half-step.  The paper's bandwidth model of 1 byte per site update (Sec. III)
-// becomes about 1/(2K) byte plus the band halo.
-//
-// A workgroup of NW wavefronts owns a band of consecutive rows; a row's words
-// are spread over its NW*64 lanes (word w = i*64*NW + wave*64 + lane).  The
-// cross-word bits (bit 0 of the next x+ word when a row's x+ neighbours are
-// shifted, and the top bit of the previous word's mask on the way back) move
-// by lane shuffle inside a wave; between waves they are exchanged once per
-// row step through LDS, with one barrier: the next-word bits of all 2K
-// half-steps of the coming step are known at the end of the current one, and
-// the carries of the current step are needed only by later steps.
-//
-// A band [y0, y1) also applies half-step h to the halo rows y0-2K+h..y0-1 and
-// y1..y1+2K-2-h, which its own rows depend on; the counter-based random words make those
-// recomputations identical to the neighbouring bands' updates.  Bands read
-// beyond their edges, so a pass reads `src` and writes `dst` (out of place);
-// every row of dst is written by exactly one band.
-#include <utility>
-
-#include "halfstep.hpp"
-#include "sca_internal.hpp"
+// fused.hip -- dispatch of the temporally blocked passes (kernel in fused.hpp);
+// passes of 1..4 MCS are instantiated here, deeper ones in fused_deep.hip.
+#include "fused.hpp"
 
 namespace sca {
-namespace {
 
-// Calls f(integral_constant<u>, s + u) for u = 0 .. sizeof...(U)-1.
-template <class F, int... U>
-__device__ __forceinline__ void unrolled_steps(F& f, int s, std::integer_sequence<int, U...>)
+int max_fused_depth(int32_t W, bool draw_free)
 {
-    (f(std::integral_constant<int, U>{}, s + U), ...);
+    if (!draw_free) return kMaxDepthRandom;
+    return W == 1024 ? kMaxDepthWide : kMaxDepthFixed;
 }
 
-// Lane i receives v from lane i+1; lane 63 keeps `edge` (DPP wavefront shift).
-__device__ __forceinline__ uint32_t from_next_lane_or(uint32_t v, uint32_t edge)
+bool fused_supported(int32_t W, int64_t Y, int32_t band, int32_t depth, bool draw_free)
 {
-    return (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)v, 0x130 /* wave_shl:1 */, 0xf, 0xf, false);
-}
-
-// Lane i receives v from lane i-1; lane 0 receives 0.
-__device__ __forceinline__ uint32_t from_prev_lane_or_zero(uint32_t v)
-{
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138 /* wave_shr:1 */, 0xf, 0xf, true);
-}
-
-__device__ __forceinline__ uint64_t join(uint32_t lo, uint32_t hi) { return (uint64_t)lo | ((uint64_t)hi << 32); }
-
-// One half-step of one window row.  A, B: on-site x- and y- slopes; C: y+
-// slopes (the next row's other-sublattice y- words); D: x+ slopes (this row's
-// other-sublattice x- words).  SH: the row's x+ neighbours sit one site
-// further (bit k+1, across the word edge).  nbits: lane 63's next-word bits,
-// slot i in bit i.  In shifted rows the top mask bits are or-ed into msb_acc
-// at bit `at` + i, and lane 0's incoming carry is left for the caller.
-template <bool SH, int G, int I, XiMode MODE, bool HASQ>
-__device__ __forceinline__ void window_halfstep(const SweepArgs& ah, int rr, int gl, uint64_t (&A)[I],
-                                                uint64_t (&B)[I], uint64_t (&C)[I], uint64_t (&D)[I],
-                                                uint32_t nbits, uint32_t& msb_acc, int at, uint64_t& mp0,
-                                                uint64_t& mq0)
-{
-    uint64_t XP[I], M[I];
-#pragma unroll
-    for (int i = 0; i < I; ++i) {
-        if constexpr (SH) {
-            const uint32_t lo = (uint32_t)D[i], hi = (uint32_t)(D[i] >> 32);
-            const uint32_t nl = from_next_lane_or(lo, nbits >> i);  // bit 0: the next word's bit 0
-            XP[i] = join(__builtin_amdgcn_alignbit(hi, lo, 1u), __builtin_amdgcn_alignbit(nl, hi, 1u));
-        } else {
-            XP[i] = D[i];
-        }
-    }
-    row_masks<G, I, MODE, HASQ>(ah, rr, gl, A, B, C, XP, M, mp0, mq0);
-#pragma unroll
-    for (int i = 0; i < I; ++i) {
-        if constexpr (SH) {
-            const uint32_t lo = (uint32_t)M[i], hi = (uint32_t)(M[i] >> 32);
-            const uint32_t ph = from_prev_lane_or_zero(hi);        // bit 31: the previous word's top bit
-            D[i] ^= join(__builtin_amdgcn_alignbit(lo, ph, 31u), __builtin_amdgcn_alignbit(hi, lo, 31u));
-            msb_acc |= (hi >> 31) << (at + i);
-        } else {
-            D[i] ^= M[i];
-        }
-    }
-}
-
-template <int NW, int I, int K, XiMode MODE, bool HASQ>
-__global__ __launch_bounds__(NW * 64) void mcs_block_kernel(SweepArgs a, const uint64_t* src, uint64_t* dst,
-                                                            int32_t band)
-{
-    constexpr int H = 2 * K;      // half-steps per pass
-    constexpr int R = 2 * K + 1;  // window rows
-    constexpr int NS = R + 1;     // register slots: the window and the row in flight
-    // Without per-site compares the step body is small: the sweep is unrolled
-    // NS steps deep so that the window rotates through the slots instead of
-    // being moved down one slot per step, and each unrolled step knows at
-    // compile time whether its rows are shifted.
-    constexpr bool ROT = MODE == XiMode::Fixed;
-    static_assert(H * I <= 32, "exchange bits per lane");
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    const int y0 = (int)blockIdx.x * band, y1 = y0 + band;
-    const int ymask = a.Y - 1;
-    const int64_t P = a.plane, W = a.W;
-    const uint32_t wo = (uint32_t)(wv * 64 + lane);  // slot 0's word in the row
-    // byte offset of slot i's word from the start of its row (32-bit, so the
-    // row base stays in scalar registers)
-    auto off = [&](int i) -> uint32_t { return (wo + (uint32_t)(i * 64 * NW)) * 8u; };
-    __shared__ uint32_t xa[2][NW];  // lane 0: bit 0 of the x+ words of the next step's half-steps
-    __shared__ uint32_t xb[2][NW];  // lane 63: top bits of this step's masks
-
-    // slot arrays: 0 = x-(even), 1 = x-(odd), 2 = y-(even), 3 = y-(odd)
-    uint64_t Wn[NS][4][I];
-    uint32_t nb0 = 0;  // lane 63: bit 0 of the next wave's first word, per (half-step, slot)
-    int buf = 0;
-
-    // rows below y0-2K feed no half-step the band needs: not loaded
-    auto load_row = [&](uint64_t (&row)[4][I], int r) {
-        const int rr = r & ymask;
-        if (r >= y0 - H) {
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const char* base = (const char*)(src + (c * P + rr * W));
-#pragma unroll
-                for (int i = 0; i < I; ++i) row[c][i] = *(const uint64_t*)(base + off(i));
-            }
-        } else {
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-#pragma unroll
-                for (int i = 0; i < I; ++i) row[c][i] = 0ull;
-        }
-    };
-    // from the next wave's lane 0 (the last wave continues in slot i+1 of wave 0)
-    auto take_next = [&](uint32_t v) -> uint32_t {
-        if (NW > 1 && wv < NW - 1) return v;
-        uint32_t o = 0;
-#pragma unroll
-        for (int h = 0; h < H; ++h)
-#pragma unroll
-            for (int i = 0; i < I; ++i) o |= ((v >> (h * I + (i + 1) % I)) & 1u) << (h * I + i);
-        return o;
-    };
-    // from the previous wave's lane 63 (the first wave continues from slot i-1 of the last wave)
-    auto take_prev = [&](uint32_t v) -> uint32_t {
-        if (NW > 1 && wv > 0) return v;
-        uint32_t o = 0;
-#pragma unroll
-        for (int h = 0; h < H; ++h)
-#pragma unroll
-            for (int i = 0; i < I; ++i) o |= ((v >> (h * I + (i + I - 1) % I)) & 1u) << (h * I + i);
-        return o;
-    };
-
-    // The band's rows depend on half-step h of rows y0-2K+h and up (the last
-    // half-step of row y0-1 writes y-slopes of row y0, and each earlier
-    // half-step widens the cone by one row), so half-step 0 starts on row
-    // y0-2K, which the skewed sweep reaches at step y0-4K+1.
-    const int s0 = y0 - 2 * H + 1;
-
-    // Step s (u = (s - s0) mod NS when the slots rotate, else 0) holds row
-    // s+j in slot (u+j) mod NS: rows s .. s+2K form the window, and row
-    // s+2K+1 is loaded into the slot freed by row s-1, one step ahead of use.
-    // Half-step h works on row s+2K-1-h with parity h&1, so all half-steps of
-    // a step have the same row alignment: shifted iff s+2K-1 is odd, i.e. iff
-    // s is even.  With the band a multiple of two, s0 is odd, so in the
-    // rotating sweep step u is shifted iff u is odd.
-    auto step = [&](auto U, int s) {
-        constexpr int u = decltype(U)::value;
-        if (s >= y1) return;
-        auto sl = [](int j) { return (u + j) % NS; };
-        if (s + 1 < y1) load_row(Wn[sl(H + 1)], s + 1 + H);
-        const bool shifted = ROT ? (u & 1) != 0 : (s & 1) == 0;
-        uint32_t msb_all = 0;
-#pragma unroll
-        for (int h = 0; h < H; ++h) {
-            const int j = H - 1 - h;          // window row of half-step h
-            const int r = s + j;              // its row
-            const int par = h & 1;
-            if (r < y0 - H + h) continue;     // not needed by the band's rows (and inputs not loaded)
-            const int rr = r & ymask;
-            SweepArgs ah = a;
-            ah.parity = par;
-            ah.t = a.t + (uint32_t)(h >> 1);
-            uint64_t mp0 = 0, mq0 = 0;
-            const uint32_t nbits = nb0 >> (h * I);
-            // row_masks indexes words as i*G + gl with G = 64*NW
-            if (ROT ? (u & 1) != 0 : shifted)
-                window_halfstep<true, 64 * NW, I, MODE, HASQ>(ah, rr, (int)wo, Wn[sl(j)][par], Wn[sl(j)][2 + par],
-                                                              Wn[sl(j + 1)][2 + (1 - par)], Wn[sl(j)][1 - par],
-                                                              nbits, msb_all, h * I, mp0, mq0);
-            else
-                window_halfstep<false, 64 * NW, I, MODE, HASQ>(ah, rr, (int)wo, Wn[sl(j)][par], Wn[sl(j)][2 + par],
-                                                               Wn[sl(j + 1)][2 + (1 - par)], Wn[sl(j)][1 - par],
-                                                               nbits, msb_all, h * I, mp0, mq0);
-            if (par == 0 && rr == 0 && r >= y0 && r < y1 && wo == 0) {
-                const int64_t dh = 2 * (int64_t)(mp0 & 1ull) - 2 * (int64_t)(mq0 & 1ull);
-                if (dh != 0) *a.h0 += dh;
-            }
-        }
-        // exchange: this step's top mask bits (for the first lanes' carries,
-        // shifted rows only) and the next step's next-word bits (needed only
-        // if the next step is shifted, i.e. this one is not); one barrier
-        {
-            // next step's window is rows s+1 .. s+2K+1; its half-step h x+ words
-            // are in window row H-h of the current step
-            uint32_t v = 0;
-            if (!shifted) {
-#pragma unroll
-                for (int h = 0; h < H; ++h)
-#pragma unroll
-                    for (int i = 0; i < I; ++i)
-                        v |= (uint32_t)(Wn[sl(H - h)][1 - (h & 1)][i] & 1ull) << (h * I + i);
-            }
-            uint32_t pm, nv;
-            if (NW > 1) {
-                if (lane == 0) xa[buf][wv] = v;
-                if (lane == 63) xb[buf][wv] = msb_all;
-                __syncthreads();
-                pm = (lane == 0) ? take_prev(xb[buf][(wv + NW - 1) % NW]) : 0u;
-                nv = (lane == 63) ? take_next(xa[buf][(wv + 1) % NW]) : 0u;
-                buf ^= 1;
-            } else {
-                pm = take_prev((uint32_t)__builtin_amdgcn_readlane((int)msb_all, 63));
-                nv = take_next((uint32_t)__builtin_amdgcn_readlane((int)v, 0));
-            }
-            if (shifted && lane == 0) {
-#pragma unroll
-                for (int h = 0; h < H; ++h) {
-                    const int j = H - 1 - h;
-                    const int par = h & 1;
-#pragma unroll
-                    for (int i = 0; i < I; ++i) Wn[sl(j)][1 - par][i] ^= (uint64_t)((pm >> (h * I + i)) & 1u);
-                }
-            }
-            if (lane == 63) nb0 = nv;
-        }
-        if (s >= y0) {
-            const int rr = s & ymask;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                char* base = (char*)(dst + (c * P + rr * W));
-#pragma unroll
-                for (int i = 0; i < I; ++i) *(uint64_t*)(base + off(i)) = Wn[sl(0)][c][i];
-            }
-        }
-    };
-
-    // prologue: rows s0 .. s0+2K, and the next-word bits for the first step
-    // (s0 is odd, so the first step is not shifted and needs none)
-#pragma unroll
-    for (int j = 0; j < R; ++j) load_row(Wn[j], s0 + j);
-
-    if constexpr (ROT) {
-        for (int s = s0; s < y1; s += NS) unrolled_steps(step, s, std::make_integer_sequence<int, NS>{});
-    } else {
-        for (int s = s0; s < y1; ++s) {
-            step(std::integral_constant<int, 0>{}, s);
-#pragma unroll
-            for (int j = 0; j < NS - 1; ++j)
-#pragma unroll
-                for (int c = 0; c < 4; ++c)
-#pragma unroll
-                    for (int i = 0; i < I; ++i) Wn[j][c][i] = Wn[j + 1][c][i];
-        }
-    }
-}
-
-template <int NW, int I, int K>
-hipError_t launch_block(const SweepArgs& a, XiMode mode, bool has_q, const uint64_t* src, uint64_t* dst,
-                        int32_t band, hipStream_t stream)
-{
-    const dim3 grid((unsigned)(a.Y / band));
-    const dim3 block(NW * 64);
-    if (mode == XiMode::Mask && a.ndraw == 0) {
-        if (has_q) hipLaunchKernelGGL((mcs_block_kernel<NW, I, K, XiMode::Fixed, true>), grid, block, 0, stream, a, src, dst, band);
-        else hipLaunchKernelGGL((mcs_block_kernel<NW, I, K, XiMode::Fixed, false>), grid, block, 0, stream, a, src, dst, band);
-    } else if (mode == XiMode::Mask) {
-        if (has_q) hipLaunchKernelGGL((mcs_block_kernel<NW, I, K, XiMode::Mask, true>), grid, block, 0, stream, a, src, dst, band);
-        else hipLaunchKernelGGL((mcs_block_kernel<NW, I, K, XiMode::Mask, false>), grid, block, 0, stream, a, src, dst, band);
-    } else {
-        if (has_q) hipLaunchKernelGGL((mcs_block_kernel<NW, I, K, XiMode::PerSite, true>), grid, block, 0, stream, a, src, dst, band);
-        else hipLaunchKernelGGL((mcs_block_kernel<NW, I, K, XiMode::PerSite, false>), grid, block, 0, stream, a, src, dst, band);
-    }
-    return hipGetLastError();
-}
-
-template <int K>
-hipError_t launch_depth(const SweepArgs& a, XiMode mode, bool has_q, const uint64_t* src, uint64_t* dst,
-                        int32_t band, hipStream_t stream)
-{
-    switch (a.W) {
-    case 64: return launch_block<1, 1, K>(a, mode, has_q, src, dst, band, stream);
-    case 128: return launch_block<2, 1, K>(a, mode, has_q, src, dst, band, stream);
-    case 256: return launch_block<4, 1, K>(a, mode, has_q, src, dst, band, stream);
-    case 512: return launch_block<8, 1, K>(a, mode, has_q, src, dst, band, stream);
-    case 1024: return launch_block<8, 2, K>(a, mode, has_q, src, dst, band, stream);
-    default: return hipErrorInvalidValue;
-    }
-}
-
-}  // namespace
-
-bool fused_supported(int32_t W, int64_t Y, int32_t band, int32_t depth)
-{
-    return (W == 64 || W == 128 || W == 256 || W == 512 || W == 1024) && depth >= 1 && depth <= 4 && band >= 4 &&
-           (band & (band - 1)) == 0 && (Y % band) == 0 && Y >= 2 * band && band >= 2 * depth;
+    return (W == 64 || W == 128 || W == 256 || W == 512 || W == 1024) && depth >= 1 &&
+           depth <= max_fused_depth(W, draw_free) && band >= 4 && (band & (band - 1)) == 0 && (Y % band) == 0 &&
+           Y >= 2 * band && band >= 2 * depth;
 }
 
 hipError_t launch_mcs_fused(const SweepArgs& a, XiMode mode, bool has_q, const uint64_t* src, uint64_t* dst,
                             int32_t band, int32_t depth, hipStream_t stream)
 {
-    if (!fused_supported(a.W, a.Y, band, depth) || mode == XiMode::Inject) return hipErrorInvalidValue;
+    const bool draw_free = mode == XiMode::Mask && a.ndraw == 0;
+    if (!fused_supported(a.W, a.Y, band, depth, draw_free) || mode == XiMode::Inject) return hipErrorInvalidValue;
     switch (depth) {
     case 1: return launch_depth<1>(a, mode, has_q, src, dst, band, stream);
     case 2: return launch_depth<2>(a, mode, has_q, src, dst, band, stream);
     case 3: return launch_depth<3>(a, mode, has_q, src, dst, band, stream);
-    default: return launch_depth<4>(a, mode, has_q, src, dst, band, stream);
+    case 4: return launch_depth<4>(a, mode, has_q, src, dst, band, stream);
+    default: return launch_mcs_fused_deep(a, mode, has_q, src, dst, band, depth, stream);
     }
 }
 

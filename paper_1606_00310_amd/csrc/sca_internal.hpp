@@ -13,7 +13,9 @@ hipError_t launch_halfstep(const SweepArgs& a, XiMode mode, bool has_q, hipStrea
 
 // `depth` MCS (2*depth half-steps from MCS a.t on) in one pass, reading src
 // and writing dst (both S[2][2][Y][W]); one workgroup per band of `band` rows.
-bool fused_supported(int32_t W, int64_t Y, int32_t band, int32_t depth);
+// draw_free: p and q in {0, 1} (no random words), which allows deeper passes.
+int max_fused_depth(int32_t W, bool draw_free);
+bool fused_supported(int32_t W, int64_t Y, int32_t band, int32_t depth, bool draw_free);
 hipError_t launch_mcs_fused(const SweepArgs& a, XiMode mode, bool has_q, const uint64_t* src, uint64_t* dst,
                             int32_t band, int32_t depth, hipStream_t stream);
 

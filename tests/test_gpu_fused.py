@@ -47,6 +47,43 @@ def test_fused_vs_oracle(orc, sca, X, Y, p, q, persite, depth):
     assert lat.roughness()[:3] == orc.moments(st)[:3]
 
 
+DRAW_FREE = [(1.0, 0.0), (0.0, 1.0), (1.0, 1.0)]
+
+
+@pytest.mark.parametrize("X,Y", [(8192, 32), (16384, 64), (65536, 32), (131072, 32)])
+@pytest.mark.parametrize("p,q", DRAW_FREE)
+@pytest.mark.parametrize("depth", [5, 6, 7, 8])
+def test_deep_fused_vs_oracle(orc, sca, X, Y, p, q, depth):
+    """Passes deeper than 4 MCS (draw-free p, q; lowered to 5 at X = 2^17)."""
+    _say(f"[deep] X={X} Y={Y} p={p} q={q} depth={depth}")
+    seed = 77 + X + Y
+    n = 2 * depth + 3
+    lat = sca.Lattice(X, Y, seed=seed)
+    lat.set_blocking(depth, 16)
+    lat.step(n, p, q)
+    st = orc.flat(X, Y, track_heights=False)
+    orc.run(st, n, p, q, seed=seed)
+    torch.cuda.synchronize()
+    assert np.array_equal(lat.slopes.cpu().numpy().view(np.uint64), orc.pack(st))
+    assert lat.meta() == (st.t, st.h0)
+
+
+@pytest.mark.parametrize("depth,band", [(5, 16), (6, 16), (7, 32), (8, 16), (8, 32), (8, 128)])
+@pytest.mark.parametrize("n", [16, 17, 41])
+def test_deep_fused_equals_unfused(sca, depth, band, n):
+    X, Y = 16384, 256
+    a = sca.Lattice(X, Y, seed=6)
+    b = sca.Lattice(X, Y, seed=6)
+    a.set_blocking(depth, band)
+    for lat, fuse in ((a, True), (b, False)):
+        lat.step(n, 1.0, 0.0, fuse=fuse)
+        lat.step(n, 0.9375, 0.0, fuse=fuse)   # random words: the pass depth is lowered to 4
+        lat.step(n, 1.0, 1.0, fuse=fuse)
+        lat.step(n + 2, 0.0, 1.0, fuse=fuse)
+    torch.cuda.synchronize()
+    assert torch.equal(a.slopes, b.slopes) and a.meta() == b.meta()
+
+
 @pytest.mark.parametrize("depth,band", [(1, 4), (1, 16), (1, 64), (2, 4), (2, 8), (2, 32), (3, 8), (3, 64), (4, 8),
                                         (4, 128)])
 @pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 13])
@@ -75,6 +112,6 @@ def test_fused_graph_and_disable(sca):
     torch.cuda.synchronize()
     assert torch.equal(a.slopes, b.slopes) and torch.equal(b.slopes, c.slopes)
     assert a.meta() == b.meta() == c.meta()
-    for bad in [(1, 12), (5, 8), (-2, 0)]:
+    for bad in [(1, 12), (9, 16), (-2, 0)]:
         with pytest.raises(sca.ScaError):
             a.set_blocking(*bad)
