@@ -1,7 +1,8 @@
 """Autotuner for the persistent ensemble kernel.
 
 It times each launch configuration (workgroup size, workgroups per compute
-unit, LDS budget, word tile and processing order) on a sample of the
+unit, LDS budget, word tile, processing order and the depth of the blocked
+passes over large realizations) on a sample of the
 ensemble, checks that every configuration leaves bit-identical states, and
 keeps the fastest.
 The choice is cached in a JSON file keyed by the device name and the sample's
@@ -20,12 +21,13 @@ from .batch import Batch, state_bytes
 LDS_PER_CU = 160 * 1024
 
 CANDIDATES = [
-    dict(block_threads=bt, blocks_per_cu=bpc, lds_bytes=lds, order=order, words_per_lane=wpl)
-    for bt in (256, 512, 1024)
+    dict(block_threads=bt, blocks_per_cu=bpc, lds_bytes=lds, order=order, words_per_lane=wpl, depth=depth)
+    for bt in (512, 1024)
     for bpc in (1, 2, 4)
-    for lds in (0, 16384, 65536)
+    for lds in (0, 65536)
     for order in (0,)
     for wpl in (1, 2)
+    for depth in (0, 1, 2)
     if bpc * lds <= LDS_PER_CU and bt * bpc <= 2048
 ]
 

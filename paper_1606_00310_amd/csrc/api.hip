@@ -566,7 +566,8 @@ bool valid_cfg(const sca_batch_config& c)
 {
     return (c.block_threads == 256 || c.block_threads == 512 || c.block_threads == 1024) && c.blocks_per_cu >= 1 &&
            c.blocks_per_cu <= 8 && c.lds_bytes >= 0 && c.lds_bytes <= 65536 && (c.lds_bytes % 8) == 0 &&
-           (c.order == 0 || c.order == 1) && (c.words_per_lane == 1 || c.words_per_lane == 2);
+           (c.order == 0 || c.order == 1) && (c.words_per_lane == 1 || c.words_per_lane == 2) && c.depth >= 0 &&
+           c.depth <= 2;
 }
 
 }  // namespace
@@ -582,7 +583,9 @@ struct sca_batch {
     std::vector<SlotHost> slots;
     std::vector<int32_t> free_slots;  // stack of free slot ids
     ArenaAllocator alloc;
-    sca_batch_config cfg{512, 2, 65536, 0, 1};
+    sca_batch_config cfg{512, 2, 65536, 0, 1, 2};
+    uint64_t* d_save = nullptr;     // save areas of the blocked passes, grid x save words
+    size_t save_bytes = 0;
     // device (library-owned)
     sca::BatchDesc* d_desc = nullptr;
     int32_t* d_order = nullptr;
@@ -615,6 +618,7 @@ void batch_free(sca_batch* b)
     (void)hipFree(b->d_order);
     (void)hipFree(b->d_counters);
     (void)hipFree(b->d_ws);
+    (void)hipFree(b->d_save);
     (void)hipHostFree(b->h_desc);
     (void)hipHostFree(b->h_order);
     (void)hipHostFree(b->h_count);
@@ -632,12 +636,28 @@ hipError_t capture_epoch_graph(sca_batch* b)
     }
     if (!b->capture && hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess)
         return hipErrorUnknown;
-    sca::BatchLaunch L{b->d_desc, b->d_order, b->d_counters, b->d_counters + 1, b->cfg.lds_bytes};
+    const int grid = b->num_cus * b->cfg.blocks_per_cu;
+    int32_t depth = b->cfg.depth;
+    int64_t save_words = 8 * (int64_t)depth * b->cfg.block_threads;
+    const size_t need = sizeof(uint64_t) * (size_t)save_words * (size_t)grid;
+    if (need > b->save_bytes) {  // no launch of the old graph is in flight (callers synchronize first)
+        (void)hipFree(b->d_save);
+        b->d_save = nullptr;
+        b->save_bytes = 0;
+        if (hipMalloc(&b->d_save, need) == hipSuccess) {
+            b->save_bytes = need;
+        } else {
+            (void)hipGetLastError();
+            depth = 0;  // no room for the save areas: unblocked half-steps
+            save_words = 0;
+        }
+    }
+    sca::BatchLaunch L{b->d_desc, b->d_order, b->d_counters, b->d_counters + 1, b->cfg.lds_bytes,
+                       depth,     b->d_save,  save_words};
     if (hipStreamBeginCapture(b->capture, hipStreamCaptureModeRelaxed) != hipSuccess) return hipErrorUnknown;
     hipError_t e1 = sca::launch_counter_reset(b->d_counters + 1, b->capture);
     if (e1 == hipSuccess)
-        e1 = sca::launch_ensemble(L, b->cfg.block_threads, b->cfg.words_per_lane, b->num_cus * b->cfg.blocks_per_cu,
-                                  b->capture);
+        e1 = sca::launch_ensemble(L, b->cfg.block_threads, b->cfg.words_per_lane, grid, b->capture);
     hipGraph_t graph = nullptr;
     const hipError_t e2 = hipStreamEndCapture(b->capture, &graph);
     if (e1 != hipSuccess || e2 != hipSuccess || !graph) {
@@ -706,7 +726,7 @@ int sca_batch_set_config(sca_batch* b, const sca_batch_config* cfg)
     if (b->failed) return SCA_ESTATE;
     const bool same = cfg->block_threads == b->cfg.block_threads && cfg->blocks_per_cu == b->cfg.blocks_per_cu &&
                       cfg->lds_bytes == b->cfg.lds_bytes && cfg->order == b->cfg.order &&
-                      cfg->words_per_lane == b->cfg.words_per_lane;
+                      cfg->words_per_lane == b->cfg.words_per_lane && cfg->depth == b->cfg.depth;
     if (same) return SCA_OK;
     DeviceGuard dg(b->device);
     if (!dg.ok) return bfail(b);
@@ -826,6 +846,13 @@ int batch_epoch(sca_batch* b, F mcs_of, int32_t* active_out)
                          [](const std::pair<int64_t, int32_t>& x, const std::pair<int64_t, int32_t>& y) {
                              return x.first > y.first;
                          });
+    // realizations that run as temporally blocked passes go first (the
+    // persistent kernel takes them in a phase of their own)
+    if (b->cfg.depth > 0)
+        std::stable_partition(work.begin(), work.end(), [b](const std::pair<int64_t, int32_t>& w) {
+            const SlotHost& s = b->slots[(size_t)w.second];
+            return s.desc.mode == 0 && sca::blocked_bands(s.W, (int)s.req.Y, b->cfg.depth, b->cfg.block_threads) > 0;
+        });
     for (const auto& w : work) b->h_order[count++] = w.second;
     if (active_out) *active_out = count;
     if (count == 0) return SCA_OK;

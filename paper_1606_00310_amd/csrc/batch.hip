@@ -11,7 +11,9 @@
 // States small enough for the workgroup's LDS budget are copied into LDS once
 // per epoch and all their half-steps run there; larger ones are updated in
 // place in the arena, where they stay L2 / Infinity-Cache resident while one
-// workgroup works on them.  Same-parity sites share no bond, so within a
+// workgroup works on them, and those with rows of 16..64 words run as
+// temporally blocked passes of 1 or 2 MCS (one HBM round trip per pass
+// instead of per half-step).  Same-parity sites share no bond, so within a
 // half-step every word is read and written by exactly one lane; the barrier
 // between half-steps (a workgroup-scope release/acquire) orders them.
 #include "halfstep.hpp"
@@ -19,6 +21,9 @@
 
 namespace sca {
 namespace {
+
+// Word 3 of a gfx9 buffer descriptor for untyped dword accesses.
+constexpr int32_t kBufferWord3 = 0x00020000;
 
 // Word tile: a row of W words is held by W/IW lanes with IW words each
 // (IW = 2 gives every lane two independent random-word chains; rows of one
@@ -76,6 +81,188 @@ __device__ __forceinline__ void halfstep_global(const SweepArgs& a, uint64_t* S,
     }
 }
 
+// Temporally blocked passes (K MCS each) over a realization in global memory
+// whose rows are G = W words (one word per lane of a G-lane group).  The
+// workgroup's groups each sweep one band of bh rows with a register window of
+// 2K+2 rows, as the single-lattice blocked kernel does, but in place: a band's
+// first 2K rows, which the band above reads as its lower halo, are saved
+// first and read from the save area; its last 2K rows, the upper halo of the
+// band below, are written only after a workgroup barrier that follows every
+// band's last use of its upper halo (4K row steps in; the band above writes
+// them from row step bh+2K-1 on, and bh >= 8K).  Groups beyond the number of
+// bands the lattice allows (bh >= 8K) idle but take part in the barriers.
+template <int K, bool HASQ>
+__device__ __forceinline__ void blocked_passes(SweepArgs a, uint64_t* S, uint64_t* save, uint32_t t0, int npass,
+                                               int nbands)
+{
+    constexpr int H = 2 * K, R = 2 * K + 1, NS = R + 1;
+    const int G = a.W;  // lanes per row (a power of two, 16..64): a runtime value, so that one copy of
+                        // the per-lane set-up serves every row width
+    const int g = threadIdx.x / G, gl = threadIdx.x & (G - 1);
+    const int lane = threadIdx.x & 63, gbase = lane & ~(G - 1);
+    const int nxl = gbase | ((gl + 1) & (G - 1)), pvl = gbase | ((gl - 1) & (G - 1));
+    const bool active = g < nbands;
+    const int bh = a.Y / nbands;
+    const int y0 = g * bh;
+    const int ymask = a.Y - 1;
+    const int64_t P = a.plane;
+    const int nxt = (g + 1) % nbands;
+    // Buffer descriptors for the four slope arrays and the save area (band
+    // b's first 2K rows as [b][j][c][G]): per-lane offsets stay 32-bit.
+    const int32_t plane_bytes = (int32_t)(P * 8);
+    __amdgpu_buffer_rsrc_t rs[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        rs[c] = __builtin_amdgcn_make_buffer_rsrc((void*)(S + c * P), (short)0, plane_bytes, kBufferWord3);
+    const __amdgpu_buffer_rsrc_t rsv =
+        __builtin_amdgcn_make_buffer_rsrc((void*)save, (short)0, (int32_t)(nbands * H * 4 * G * 8), kBufferWord3);
+    auto ld = [](__amdgpu_buffer_rsrc_t r, int off) -> uint64_t {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+        return (uint64_t)v[0] | ((uint64_t)v[1] << 32);
+    };
+    auto st = [](__amdgpu_buffer_rsrc_t r, int off, uint64_t w) {
+        __attribute__((ext_vector_type(2))) uint32_t v;
+        v[0] = (uint32_t)w;
+        v[1] = (uint32_t)(w >> 32);
+        __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, 0);
+    };
+    auto svoff = [&](int b, int j, int c) -> int { return (((b * H + j) * 4 + c) * G + gl) * 8; };
+    auto soff = [&](int rr) -> int { return (rr * G + gl) * 8; };
+
+    for (int pass = 0; pass < npass; ++pass) {
+        a.t = t0 + (uint32_t)(pass * K);
+        if (active) {
+            for (int j = 0; j < H; ++j)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) st(rsv, svoff(g, j, c), ld(rs[c], soff(y0 + j)));
+        }
+        __syncthreads();
+        uint64_t Wn[NS][4][1];
+        // Rows are addressed relative to the band start y0: the same for every
+        // group at a given step, so the branches below are uniform and each
+        // load keeps one buffer descriptor.  Rows below y0-2K feed no
+        // half-step the band needs; rows from y1 on come from the next band's
+        // save area.
+        auto load_row = [&](uint64_t (&row)[4][1], int rel) {
+            if (rel < -H) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) row[c][0] = 0ull;
+            } else if (rel >= bh) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) row[c][0] = ld(rsv, svoff(nxt, rel - bh, c));
+            } else {
+                const int rr = (y0 + rel) & ymask;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) row[c][0] = ld(rs[c], soff(rr));
+            }
+        };
+        if (active) {
+#pragma unroll
+            for (int j = 0; j < R; ++j) load_row(Wn[j], j - 2 * H + 1);
+        }
+        const int nsteps = bh + 2 * H - 1;  // the same for every group: uniform barriers
+        for (int k = 0; k < nsteps; ++k) {
+            if (k == 2 * H) __syncthreads();  // every band is done with its upper halo
+            if (!active) continue;
+            const int q = k - 2 * H + 1;      // this step's first window row, relative to y0
+            if (q + 1 < bh) load_row(Wn[R], q + 1 + H);
+#pragma unroll
+            for (int h = 0; h < H; ++h) {
+                const int j = H - 1 - h;
+                const int rel = q + j;
+                const int par = h & 1;
+                if (rel < -H + h) continue;
+                const int rr = (y0 + rel) & ymask;
+                const bool shifted = ((par ^ (rel & 1)) != 0);  // y0 is even
+                SweepArgs ah = a;
+                ah.parity = par;
+                ah.t = a.t + (uint32_t)(h >> 1);
+                // the row is one word per lane: the next word's bit 0 and the
+                // previous word's top mask bit come from the neighbouring lanes of
+                // the group, wrapping at the row end
+                uint64_t(&D)[1] = Wn[j][1 - par];
+                uint64_t XP[1], M[1], mp0 = 0, mq0 = 0;
+                const uint32_t nxt = (uint32_t)__shfl((int)(uint32_t)(D[0] & 1ull), nxl);
+                XP[0] = shifted ? ((D[0] >> 1) | ((uint64_t)nxt << 63)) : D[0];
+                row_masks<1, 1, XiMode::Mask, HASQ>(ah, rr, gl, Wn[j][par], Wn[j][2 + par], Wn[j + 1][2 + (1 - par)],
+                                                     XP, M, mp0, mq0);
+                const uint32_t prv = (uint32_t)__shfl((int)(uint32_t)(M[0] >> 63), pvl);
+                D[0] ^= shifted ? ((M[0] << 1) | (uint64_t)prv) : M[0];
+                if (par == 0 && rel == 0 && g == 0 && gl == 0) {  // site (0,0)
+                    const int64_t dh = 2 * (int64_t)(mp0 & 1ull) - 2 * (int64_t)(mq0 & 1ull);
+                    if (dh != 0) *a.h0 += dh;
+                }
+            }
+            if (q >= 0) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) st(rs[c], soff(y0 + q), Wn[0][c][0]);
+            }
+#pragma unroll
+            for (int j = 0; j < NS - 1; ++j)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) Wn[j][c][0] = Wn[j + 1][c][0];
+        }
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ void blocked_dispatch(const SweepArgs& a, uint64_t* S, uint64_t* save, uint32_t t0,
+                                                 int npass, int nbands, int K, bool has_q)
+{
+    if (K == 1) {
+        if (has_q) blocked_passes<1, true>(a, S, save, t0, npass, nbands);
+        else blocked_passes<1, false>(a, S, save, t0, npass, nbands);
+    } else {
+        if (has_q) blocked_passes<2, true>(a, S, save, t0, npass, nbands);
+        else blocked_passes<2, false>(a, S, save, t0, npass, nbands);
+    }
+}
+
+__device__ __forceinline__ SweepArgs args_of(const BatchDesc& d)
+{
+    SweepArgs a{};
+    a.plane = d.plane;
+    a.W = d.W;
+    a.Y = d.Y;
+    a.nb = d.nb;
+    a.k0 = d.k0;
+    a.k1 = d.k1;
+    a.dig_p = d.dig_p;
+    a.dig_q = d.dig_q;
+    a.ndraw = d.ndraw;
+    a.all_p = d.all_p;
+    a.all_q = d.all_q;
+    a.thr_p = d.thr_p;
+    a.thr_q = d.thr_q;
+    a.h0 = d.h0;
+    return a;
+}
+
+// The descriptor of an item, moved into scalar registers: it is the same for
+// the whole workgroup, and buffer descriptors built from it must be uniform.
+__device__ __forceinline__ BatchDesc load_desc(const BatchLaunch& L, int32_t item)
+{
+    static_assert(sizeof(BatchDesc) % 4 == 0, "descriptor of whole dwords");
+    const BatchDesc d = L.desc[L.order[item]];
+    uint32_t w[sizeof(BatchDesc) / 4];
+    __builtin_memcpy(w, &d, sizeof(BatchDesc));
+#pragma unroll
+    for (unsigned i = 0; i < sizeof(BatchDesc) / 4; ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+    BatchDesc u;
+    __builtin_memcpy(&u, w, sizeof(BatchDesc));
+    return u;
+}
+
+// The next item of the work queue, the same for the whole workgroup.
+__device__ __forceinline__ int32_t next_item(int32_t* queue, int32_t* s_item)
+{
+    __syncthreads();  // the previous realization is finished (LDS and s_item reuse)
+    if (threadIdx.x == 0) *s_item = atomicAdd(queue, 1);
+    __syncthreads();
+    // uniform: the descriptor then loads into scalar registers
+    return __builtin_amdgcn_readfirstlane(*s_item);
+}
+
 template <int BLOCK, int IW>
 __global__ __launch_bounds__(BLOCK) void ensemble_kernel(BatchLaunch L)
 {
@@ -86,30 +273,35 @@ __global__ __launch_bounds__(BLOCK) void ensemble_kernel(BatchLaunch L)
     const int wave = threadIdx.x >> 6;
     const int32_t n_items = *L.n_items;
 
-    for (;;) {
-        __syncthreads();  // the previous realization is finished (LDS and s_item reuse)
-        if (threadIdx.x == 0) s_item = atomicAdd(L.queue, 1);
-        __syncthreads();
-        const int32_t item = s_item;
-        if (item >= n_items) break;  // every wave of every workgroup gets here once the counter passes n
-        const BatchDesc d = L.desc[L.order[item]];
-        if (d.n_run == 0) continue;
+    // Phase 1: realizations that run as temporally blocked passes (the host
+    // orders them first): passes of L.depth MCS, and one of a single MCS for
+    // an odd remainder.  The first other item moves the workgroup on to
+    // phase 2, which handles any realization.  Keeping the two loops apart
+    // keeps their register needs apart.
+    int32_t item = next_item(L.queue, &s_item);
+    while (item < n_items) {
+        const BatchDesc d = load_desc(L, item);
+        const int nbands = d.mode == 0 ? blocked_bands(d.W, d.Y, L.depth, BLOCK) : 0;
+        if (nbands == 0) break;
+        if (d.n_run > 0) {
+            const SweepArgs a = args_of(d);
+            const bool has_q = d.has_q != 0;
+            uint64_t* save = L.save + (int64_t)blockIdx.x * L.save_words;
+            const int npass = (int)(d.n_run / (uint32_t)L.depth);
+            if (npass > 0) blocked_dispatch(a, d.S, save, d.t, npass, nbands, L.depth, has_q);
+            const uint32_t done = (uint32_t)npass * (uint32_t)L.depth;
+            if (done < d.n_run) blocked_dispatch(a, d.S, save, d.t + done, (int)(d.n_run - done), nbands, 1,
+                                                        has_q);
+        }
+        item = next_item(L.queue, &s_item);
+    }
 
-        SweepArgs a{};
-        a.plane = d.plane;
-        a.W = d.W;
-        a.Y = d.Y;
-        a.nb = d.nb;
-        a.k0 = d.k0;
-        a.k1 = d.k1;
-        a.dig_p = d.dig_p;
-        a.dig_q = d.dig_q;
-        a.ndraw = d.ndraw;
-        a.all_p = d.all_p;
-        a.all_q = d.all_q;
-        a.thr_p = d.thr_p;
-        a.thr_q = d.thr_q;
-        a.h0 = d.h0;
+    // Phase 2: every other realization, half-step by half-step, in LDS or in
+    // the arena.
+    for (; item < n_items; item = next_item(L.queue, &s_item)) {
+        const BatchDesc d = load_desc(L, item);
+        if (d.n_run == 0) continue;
+        SweepArgs a = args_of(d);
         const bool has_q = d.has_q != 0;
         const int64_t words = 4 * d.plane;
         const bool in_lds = d.W <= 8 && words * 8 <= (int64_t)L.lds_bytes;

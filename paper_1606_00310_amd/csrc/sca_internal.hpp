@@ -66,7 +66,22 @@ struct BatchLaunch {
     const int32_t* n_items;  // number of entries of order to process
     int32_t* queue;          // work counter, reset to 0 before each launch
     int32_t lds_bytes;       // dynamic LDS per workgroup; states up to this size run from LDS
+    int32_t depth;           // MCS per blocked pass in global memory (0: none)
+    uint64_t* save;          // per-workgroup save areas for the blocked passes
+    int64_t save_words;      // words per workgroup: 8 * depth * block threads
 };
+
+// Bands of the temporally blocked ensemble passes of depth K over a
+// realization with dyadic p, q and rows of W words, for workgroups of
+// block_threads (0: it runs unblocked): one band per group of W lanes, at
+// least 8K rows each.
+__host__ __device__ inline int blocked_bands(int W, int Y, int K, int block_threads)
+{
+    if (K <= 0 || (W != 16 && W != 32 && W != 64)) return 0;
+    int nb = block_threads / W;
+    while (nb > 1 && Y / nb < 8 * K) nb >>= 1;
+    return (nb >= 2 && Y / nb >= 8 * K) ? nb : 0;
+}
 
 hipError_t launch_ensemble(const BatchLaunch& L, int block_threads, int words_per_lane, int grid, hipStream_t stream);
 hipError_t launch_counter_reset(int32_t* counter, hipStream_t stream);

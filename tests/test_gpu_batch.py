@@ -36,6 +36,9 @@ def _reals():
         R(8192, 8, 0.75, 0.25, 13, 10), R(32, 1024, 1.0, 0.0, 17, 11), R(128, 4, 0.5, 0.0, 0, 12),
         R(256, 64, 0.5, 0.0, 21, 13, True), R(64, 4096, 0.1875, 0.0, 8, 2**40 + 5), R(16, 16, 0.0, 1.0, 5, 14),
         R(512, 128, 0.9375, 0.0625, 12, 15),
+        # rows of 16..64 words: temporally blocked passes when the configuration's depth is > 0
+        R(2048, 512, 0.75, 0.25, 7, 16), R(4096, 256, 0.5, 0.0, 5, 17), R(8192, 128, 0.9375, 0.0625, 4, 18),
+        R(2048, 64, 0.5, 0.0, 9, 19), R(8192, 32, 1.0, 0.0, 6, 20), R(2048, 1024, 0.93, 0.07, 3, 21),
     ]
 
 
@@ -57,17 +60,18 @@ def solo_states(sca):
 
 
 CONFIGS = [
-    dict(block_threads=512, blocks_per_cu=2, lds_bytes=65536, order=0, words_per_lane=1),
-    dict(block_threads=256, blocks_per_cu=4, lds_bytes=65536, order=1, words_per_lane=2),
-    dict(block_threads=1024, blocks_per_cu=1, lds_bytes=0, order=0, words_per_lane=1),
-    dict(block_threads=1024, blocks_per_cu=1, lds_bytes=0, order=0, words_per_lane=2),
-    dict(block_threads=512, blocks_per_cu=1, lds_bytes=16384, order=1, words_per_lane=2),
-    dict(block_threads=256, blocks_per_cu=8, lds_bytes=4096, order=0, words_per_lane=1),
+    dict(block_threads=512, blocks_per_cu=2, lds_bytes=65536, order=0, words_per_lane=1, depth=2),
+    dict(block_threads=256, blocks_per_cu=4, lds_bytes=65536, order=1, words_per_lane=2, depth=1),
+    dict(block_threads=1024, blocks_per_cu=1, lds_bytes=0, order=0, words_per_lane=1, depth=0),
+    dict(block_threads=1024, blocks_per_cu=1, lds_bytes=0, order=0, words_per_lane=2, depth=2),
+    dict(block_threads=512, blocks_per_cu=1, lds_bytes=16384, order=1, words_per_lane=2, depth=0),
+    dict(block_threads=256, blocks_per_cu=8, lds_bytes=4096, order=0, words_per_lane=1, depth=2),
+    dict(block_threads=1024, blocks_per_cu=2, lds_bytes=0, order=0, words_per_lane=1, depth=1),
 ]
 
 
 @pytest.mark.parametrize("cfg", CONFIGS,
-                         ids=lambda c: "b{block_threads}-c{blocks_per_cu}-l{lds_bytes}-o{order}-w{words_per_lane}".format(**c))
+                         ids=lambda c: "b{block_threads}-c{blocks_per_cu}-l{lds_bytes}-o{order}-w{words_per_lane}-d{depth}".format(**c))
 @pytest.mark.parametrize("epoch", [5, 1000])
 def test_batch_equals_solo(sca, solo_states, cfg, epoch):
     from paper_1606_00310_amd.batch import Batch, state_bytes
@@ -92,7 +96,7 @@ def test_batch_equals_solo(sca, solo_states, cfg, epoch):
 def test_batch_matches_oracle(orc, sca):
     from paper_1606_00310_amd.batch import Batch, state_bytes
 
-    reals = [r for r in _reals() if r.sites <= 1 << 16]
+    reals = [r for r in _reals() if r.sites <= 1 << 18]
     b = Batch(max_slots=len(reals), arena_bytes=sum(state_bytes(r.X, r.Y) for r in reals))
     slots = b.admit(reals)
     while b.run(7):
