@@ -127,7 +127,7 @@ def cpu_baseline(X, Y, p, q, seed, rows, budget_s, max_mcs=200):
                       f"in {dt:.1f} s"}
 
 
-def bench_ensemble(torch, P, n=4096, solo_per_L=3, tune_sample=512, tune_mcs=100, serving=True, solo=True):
+def bench_ensemble(torch, P, n=4096, solo_per_L=3, tune_scale=10, serving=True, solo=True):
     """The 4096-realization ensemble in one persistent launch vs one launch
     (graph-captured MCS loop) per realization, and a serving run."""
     from paper_1606_00310_amd import autotune, serve
@@ -137,7 +137,10 @@ def bench_ensemble(torch, P, n=4096, solo_per_L=3, tune_sample=512, tune_mcs=100
     members = ensemble(n)
     reals = [Realization(m.L, m.L, m.p, 0.0, m.n_mcs, m.seed) for m in members]
     work = sum(r.sites * r.n_mcs for r in reals)
-    sample = [Realization(r.X, r.Y, r.p, r.q, min(r.n_mcs, tune_mcs), r.seed) for r in reals[:tune_sample]]
+    # The autotuner runs the whole ensemble with every MCS budget divided by
+    # tune_scale: the same mix of sizes and the same ratio of the longest
+    # realization (the critical path of one workgroup) to the total work.
+    sample = [Realization(r.X, r.Y, r.p, r.q, max(1, r.n_mcs // tune_scale), r.seed) for r in reals]
     cfg, table = autotune.autotune(sample, cache_path=None)
 
     b = Batch(max_slots=len(reals), arena_bytes=sum(state_bytes(r.X, r.Y) for r in reals), config=cfg)

@@ -208,12 +208,13 @@ typedef struct sca_batch_config {
     int32_t order;         /* 0: longest remaining work first, 1: slot order */
     int32_t words_per_lane;/* word tile: 64-site words per lane in a row, 1 or 2 */
     int32_t depth;         /* realizations in global memory with dyadic p, q and
-                              2048 <= X <= 8192 run as temporally blocked
+                              1024 <= X <= 8192 run as temporally blocked
                               passes of `depth` MCS (0 = never, 1 or 2): one
                               band per group of X/128 lanes, at least 8*depth
-                              rows each.  For depth > 0 the library allocates a
-                              save area of 64*depth*block_threads bytes per
-                              persistent workgroup. */
+                              rows each (groups beyond Y/(8*depth) bands idle).
+                              For depth > 0 the library allocates a save area
+                              of 64*depth*block_threads bytes per persistent
+                              workgroup. */
 } sca_batch_config;
 
 typedef struct sca_slot_info {

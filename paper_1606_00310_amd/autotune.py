@@ -2,9 +2,11 @@
 
 It times each launch configuration (workgroup size, workgroups per compute
 unit, LDS budget, word tile, processing order and the depth of the blocked
-passes over large realizations) on a sample of the
-ensemble, checks that every configuration leaves bit-identical states, and
-keeps the fastest.
+passes over large realizations) on a sample of the ensemble, checks that
+every configuration leaves bit-identical states, and keeps the fastest.  The
+sample should keep the ensemble's mix: with the MCS budgets scaled down
+uniformly it has the same ratio of the longest realization (which one
+workgroup runs alone) to the total work, so the ranking carries over.
 The choice is cached in a JSON file keyed by the device name and the sample's
 signature.
 """

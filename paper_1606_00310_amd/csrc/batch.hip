@@ -11,7 +11,7 @@
 // States small enough for the workgroup's LDS budget are copied into LDS once
 // per epoch and all their half-steps run there; larger ones are updated in
 // place in the arena, where they stay L2 / Infinity-Cache resident while one
-// workgroup works on them, and those with rows of 16..64 words run as
+// workgroup works on them, and those with rows of 8..64 words run as
 // temporally blocked passes of 1 or 2 MCS (one HBM round trip per pass
 // instead of per half-step).  Same-parity sites share no bond, so within a
 // half-step every word is read and written by exactly one lane; the barrier
@@ -96,7 +96,7 @@ __device__ __forceinline__ void blocked_passes(SweepArgs a, uint64_t* S, uint64_
                                                int nbands)
 {
     constexpr int H = 2 * K, R = 2 * K + 1, NS = R + 1;
-    const int G = a.W;  // lanes per row (a power of two, 16..64): a runtime value, so that one copy of
+    const int G = a.W;  // lanes per row (a power of two, 8..64): a runtime value, so that one copy of
                         // the per-lane set-up serves every row width
     const int g = threadIdx.x / G, gl = threadIdx.x & (G - 1);
     const int lane = threadIdx.x & 63, gbase = lane & ~(G - 1);

@@ -72,12 +72,12 @@ struct BatchLaunch {
 };
 
 // Bands of the temporally blocked ensemble passes of depth K over a
-// realization with dyadic p, q and rows of W words, for workgroups of
+// realization with dyadic p, q and rows of W = 8..64 words, for workgroups of
 // block_threads (0: it runs unblocked): one band per group of W lanes, at
 // least 8K rows each.
 __host__ __device__ inline int blocked_bands(int W, int Y, int K, int block_threads)
 {
-    if (K <= 0 || (W != 16 && W != 32 && W != 64)) return 0;
+    if (K <= 0 || (W != 8 && W != 16 && W != 32 && W != 64)) return 0;
     int nb = block_threads / W;
     while (nb > 1 && Y / nb < 8 * K) nb >>= 1;
     return (nb >= 2 && Y / nb >= 8 * K) ? nb : 0;
