@@ -214,3 +214,15 @@ def test_work_quota_epochs_equal_solo(sca, solo_states):
         assert torch.equal(S, ref), r
         assert int(h[0]) == h0
     b.close()
+
+
+def test_autotune_small(sca):
+    """The autotuner times each candidate on the sample, checks that all of
+    them leave the same states, and returns the fastest."""
+    from paper_1606_00310_amd import autotune
+    from paper_1606_00310_amd.batch import Realization as R
+
+    sample = [R(2048, 256, 0.75, 0.0, 6, 300), R(64, 64, 0.5, 0.0, 9, 301), R(1024, 1024, 0.9375, 0.0625, 5, 302)]
+    cands = [autotune.CANDIDATES[0], autotune.CANDIDATES[2], autotune.CANDIDATES[-1]]
+    best, table = autotune.autotune(sample, candidates=cands, cache_path=None)
+    assert best in cands and len(table) == 3 and all(t > 0 for _, t in table)
