@@ -291,12 +291,12 @@ def main():
 
     w = HEADLINE
     K, Wm = args.steps, args.warmup
-    # The sweep runs as temporally blocked passes of DEPTH MCS each (all ten
-    # half-steps of five MCS in one sweep over the state, BAND-row bands per
+    # The sweep runs as temporally blocked passes of DEPTH MCS each (all twelve
+    # half-steps of six MCS in one sweep over the state, BAND-row bands per
     # workgroup), an even number of passes per call; the MCS left over run as
     # two half-step launches each.  Both kinds of launch read the packed state
     # once and write it once: X*Y/4 bytes each way.
-    DEPTH, BAND = 5, 128
+    DEPTH, BAND = 6, 128
     n_pass = (K // DEPTH) & ~1
     n_fused = n_pass * DEPTH
     torch.cuda.synchronize()

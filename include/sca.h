@@ -93,10 +93,12 @@ int sca_init(sca_ctx** out, int64_t X, int64_t Y, uint64_t seed, void* slopes_de
  * For X >= 8192 groups of MCS run as fused passes (all half-steps of
  * `depth` MCS in one sweep over the state, out of place into the library's
  * second buffer and back; see sca_set_blocking), which divides the HBM
- * traffic per MCS by about 2*depth; the results are bit-identical to the
- * two-launch form, and S holds the state when the enqueued work has run.  If
- * the second buffer cannot be allocated the call falls back to two launches
- * per MCS. */
+ * traffic per MCS by about 2*depth.  The passes come in an even number so
+ * that S holds the state when the enqueued work has run: whole passes of
+ * `depth` MCS, then the remainder r as two passes of ceil(r/2) and
+ * floor(r/2) MCS, or two half-step launches when r = 1.  The results are
+ * bit-identical to the two-launch form.  If the second buffer cannot be
+ * allocated the call falls back to two launches per MCS. */
 int sca_step(sca_ctx* ctx, int64_t n_mcs, double p, double q);
 
 /* sca_step with flags (SCA_FORCE_PERSITE, SCA_STEP_GRAPH).  With
@@ -140,11 +142,11 @@ int sca_get_meta(sca_ctx* ctx, int64_t* t, int64_t* h0);
  * 128, 64, 32, 16, 8 that leaves enough workgroups to fill the chip).
  * Passes run at most 8 MCS deep when p and q are both 0 or 1 (no random
  * words; at most 5 for X = 2^17), and at most 4 deep otherwise: a larger
- * depth is lowered to that limit when sca_step runs.  The automatic depth is
- * 5 without random words and 3 with them on bands of >= 64 rows, 3 on 32-row
- * bands, 2 on 16 and 1 on smaller ones; the per-site path (non-dyadic p or
- * q), which is ALU-bound, is never fused.  Any setting gives bit-identical
- * results. */
+ * depth is lowered to that limit when sca_step runs.  The automatic depth
+ * without random words is 6 on bands of >= 128 rows (5 at X = 2^17) and 5 on
+ * 64-row bands; with random words 3 on bands of >= 32 rows; 2 on 16-row
+ * bands and 1 on smaller ones; the per-site path (non-dyadic p or q), which
+ * is ALU-bound, is never fused.  Any setting gives bit-identical results. */
 int sca_set_blocking(sca_ctx* ctx, int32_t depth, int32_t band);
 
 /* Sets the MCS counter (for resuming from a saved state; the caller restores

@@ -254,8 +254,7 @@ int sca_step_ex(sca_ctx* c, int64_t n_mcs, double p, double q, unsigned flags)
     const int64_t t0 = c->t;
     // Groups of `depth` MCS run as fused passes alternating S -> alt -> S (one
     // HBM pass per group); the number of passes is kept even so that the
-    // caller's S holds the state after the call, and the remaining MCS run as
-    // two in-place half-step launches each.
+    // caller's S holds the state after the call (see the remainder below).
     // Automatic choice: a band per workgroup with enough workgroups to fill
     // the chip and bands as tall as that allows; deep passes on tall bands
     // (the halo costs 4*depth rows per band), shallower ones on short bands.
@@ -269,13 +268,14 @@ int sca_step_ex(sca_ctx* c, int64_t n_mcs, double p, double q, unsigned flags)
     }
     // Without random words (p, q in {0, 1}) a pass is bandwidth-bound and
     // costs about the same at any depth whose window fits the registers of
-    // two workgroups per compute unit, which is 5 MCS; passes with draws are
-    // ALU-bound and do best at 3.
+    // two workgroups per compute unit, which is 6 MCS (5 at X = 2^17); passes
+    // with draws are ALU-bound and do best at 3.
     const bool draw_free = !persite && a.ndraw == 0;
     const int32_t dmax = sca::max_fused_depth(c->W, draw_free);
     int32_t depth = c->depth;
     if (depth < 0) {
         depth = persite ? 0
+                        : band >= 128 ? (draw_free ? 6 : 3)
                         : band >= 64 ? (draw_free ? 5 : 3)
                         : band >= 32 ? 3
                         : band >= 16 ? 2
@@ -284,7 +284,7 @@ int sca_step_ex(sca_ctx* c, int64_t n_mcs, double p, double q, unsigned flags)
     if (depth > dmax) {
         depth = dmax;
     }
-    bool fuse = !(flags & SCA_NO_FUSE) && depth > 0 && n_mcs >= 2 * (int64_t)depth &&
+    bool fuse = !(flags & SCA_NO_FUSE) && depth > 0 && n_mcs >= 2 &&
                 sca::fused_supported(c->W, c->Y, band, depth, draw_free);
     if (fuse && !c->alt) {
         if (hipMalloc(&c->alt, sizeof(uint64_t) * (size_t)(4 * c->Y * c->W)) != hipSuccess) {
@@ -293,16 +293,25 @@ int sca_step_ex(sca_ctx* c, int64_t n_mcs, double p, double q, unsigned flags)
             fuse = false;  // not enough memory for the second state: unfused launches
         }
     }
+    // An even number of `depth`-MCS passes, then the remainder r < 2*depth as
+    // two passes of ceil(r/2) and floor(r/2) MCS (still an even count), or, for
+    // r = 1, as two half-step launches.
     const int64_t n_pass = fuse ? ((n_mcs / depth) & ~(int64_t)1) : 0;
+    const int64_t rem = n_mcs - n_pass * depth;
+    const int32_t tail1 = (fuse && rem >= 2) ? (int32_t)((rem + 1) / 2) : 0;
+    const int32_t tail2 = (fuse && rem >= 2) ? (int32_t)(rem / 2) : 0;
+    const int64_t n_fused = n_pass * depth + tail1 + tail2;
     auto enqueue = [&](hipStream_t st) -> hipError_t {
-        for (int64_t i = 0; i < n_pass; ++i) {
-            a.t = (uint32_t)(t0 + i * depth);
+        for (int64_t i = 0; i < n_pass + (tail1 ? 2 : 0); ++i) {
+            const bool tail = i >= n_pass;
+            const int32_t d = !tail ? depth : (i == n_pass ? tail1 : tail2);
+            a.t = (uint32_t)(t0 + (!tail ? i * depth : n_pass * depth + (i == n_pass ? 0 : tail1)));
             const bool fwd = (i & 1) == 0;
             const hipError_t e = sca::launch_mcs_fused(a, mode, has_q, fwd ? c->S : c->alt, fwd ? c->alt : c->S,
-                                                       band, depth, st);
+                                                       band, d, st);
             if (e != hipSuccess) return e;
         }
-        for (int64_t i = n_pass * depth; i < n_mcs; ++i) {
+        for (int64_t i = n_fused; i < n_mcs; ++i) {
             a.t = (uint32_t)(t0 + i);
             for (int parity = 0; parity < 2; ++parity) {
                 a.parity = parity;

@@ -101,9 +101,16 @@ __device__ __forceinline__ void window_halfstep(const SweepArgs& ah, int rr, int
     }
 }
 
+// Two 512-thread workgroups per CU need at most 128 VGPRs.  The 6-MCS window
+// needs a few more: the compiler is asked to fit it anyway (about five
+// spilled values) rather than drop to one workgroup per CU, which is 10 %
+// faster at 65536^2.  The 7-MCS window spills too much for that to pay.
+template <int I, int K>
+constexpr int kMinWavesPerEU = (I == 1 && K == 6) ? 4 : 1;
+
 template <int NW, int I, int K, XiMode MODE, bool HASQ>
-__global__ __launch_bounds__(NW * 64) void mcs_block_kernel(SweepArgs a, const uint64_t* src, uint64_t* dst,
-                                                            int32_t band)
+__global__ __launch_bounds__(NW * 64, (kMinWavesPerEU<I, K>)) void mcs_block_kernel(SweepArgs a, const uint64_t* src,
+                                                                                   uint64_t* dst, int32_t band)
 {
     constexpr int H = 2 * K;      // half-steps per pass
     constexpr int R = 2 * K + 1;  // window rows
