@@ -26,12 +26,15 @@ __device__ __forceinline__ u32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
     constexpr uint32_t kWeylB = 0xBB67AE85u;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t hiA = __umulhi(kMulA, c0);
-        const uint32_t loA = kMulA * c0;
-        const uint32_t hiB = __umulhi(kMulB, c2);
-        const uint32_t loB = kMulB * c2;
-        const uint32_t n0 = hiB ^ c1 ^ k0;
-        const uint32_t n2 = hiA ^ c3 ^ k1;
+        // One 32x32->64 product gives both halves (v_mad_u64_u32, full rate on
+        // gfx950, where separate mul_hi and mul_lo take two instructions), and
+        // each three-way xor is one v_bitop3_b32 (truth table 0x96).
+        const uint64_t pA = (uint64_t)kMulA * c0;
+        const uint64_t pB = (uint64_t)kMulB * c2;
+        const uint32_t hiA = (uint32_t)(pA >> 32), loA = (uint32_t)pA;
+        const uint32_t hiB = (uint32_t)(pB >> 32), loB = (uint32_t)pB;
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32(hiB, c1, k0, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32(hiA, c3, k1, 0x96);
         c0 = n0;
         c1 = loB;
         c2 = n2;
