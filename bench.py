@@ -291,12 +291,12 @@ def main():
 
     w = HEADLINE
     K, Wm = args.steps, args.warmup
-    # The sweep runs as temporally blocked passes of DEPTH MCS each (all twelve
-    # half-steps of six MCS in one sweep over the state, BAND-row bands per
-    # workgroup), an even number of passes per call; the MCS left over run as
-    # two half-step launches each.  Both kinds of launch read the packed state
-    # once and write it once: X*Y/4 bytes each way.
-    DEPTH, BAND = 6, 128
+    # The sweep runs as temporally blocked passes of DEPTH MCS each (all
+    # sixteen half-steps of eight MCS in one sweep over the state, BAND-row
+    # bands per workgroup), an even number of passes per call; the MCS left
+    # over run as two shallower passes.  Every pass reads the packed state once
+    # and writes it once: X*Y/4 bytes each way.
+    DEPTH, BAND = 8, 256
     n_pass = (K // DEPTH) & ~1
     n_fused = n_pass * DEPTH
     torch.cuda.synchronize()
@@ -310,7 +310,7 @@ def main():
     alg_bytes = w.sites // 2
     if n_pass:
         avg_ms = fused_ms / n_pass
-        kernel = f"mcs_block_kernel<8,1,{DEPTH},Fixed,false>"
+        kernel = f"mcs_block_lds_kernel<8,{DEPTH},false>"
         per_update = alg_bytes / (w.sites * DEPTH)
     else:
         avg_ms = ms / (2 * K)

@@ -255,27 +255,28 @@ int sca_step_ex(sca_ctx* c, int64_t n_mcs, double p, double q, unsigned flags)
     // Groups of `depth` MCS run as fused passes alternating S -> alt -> S (one
     // HBM pass per group); the number of passes is kept even so that the
     // caller's S holds the state after the call (see the remainder below).
-    // Automatic choice: a band per workgroup with enough workgroups to fill
-    // the chip and bands as tall as that allows; deep passes on tall bands
-    // (the halo costs 4*depth rows per band), shallower ones on short bands.
-    // The per-site path is ALU-bound and runs unfused.
+    // Automatic choice: a band per workgroup with enough waves to fill the
+    // chip and bands as tall as that allows; deep passes on tall bands (the
+    // halo costs 4*depth rows per band), shallower ones on short bands.  The
+    // per-site path is ALU-bound and runs unfused.
     const int64_t nw = c->W >= 512 ? 8 : (c->W >= 64 ? c->W / 64 : 1);
+    // Without random words (p, q in {0, 1}) a pass is bandwidth-bound and
+    // deeper passes cost little more than shallow ones: rows of one word per
+    // lane (X <= 2^16) take the LDS-window kernel at 8 MCS (5 at X = 2^17) on
+    // bands of up to 256 rows (about one 512-thread workgroup per CU); passes
+    // with draws are ALU-bound and do best at 3 MCS on bands of up to 128 rows.
+    const bool draw_free = !persite && a.ndraw == 0;
     int32_t band = c->band;
     if (band == 0) {
-        int64_t b = 128;
+        int64_t b = draw_free ? 256 : 128;
         while (b > 8 && c->Y / b < 2048 / nw) b >>= 1;
         band = (int32_t)b;
     }
-    // Without random words (p, q in {0, 1}) a pass is bandwidth-bound and
-    // costs about the same at any depth whose window fits the registers of
-    // two workgroups per compute unit, which is 6 MCS (5 at X = 2^17); passes
-    // with draws are ALU-bound and do best at 3.
-    const bool draw_free = !persite && a.ndraw == 0;
     const int32_t dmax = sca::max_fused_depth(c->W, draw_free);
     int32_t depth = c->depth;
     if (depth < 0) {
         depth = persite ? 0
-                        : band >= 128 ? (draw_free ? 6 : 3)
+                        : band >= 128 ? (draw_free ? 8 : 3)
                         : band >= 64 ? (draw_free ? 5 : 3)
                         : band >= 32 ? 3
                         : band >= 16 ? 2

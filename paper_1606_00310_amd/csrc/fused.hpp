@@ -101,16 +101,9 @@ __device__ __forceinline__ void window_halfstep(const SweepArgs& ah, int rr, int
     }
 }
 
-// Two 512-thread workgroups per CU need at most 128 VGPRs.  The 6-MCS window
-// needs a few more: the compiler is asked to fit it anyway (about five
-// spilled values) rather than drop to one workgroup per CU, which is 10 %
-// faster at 65536^2.  The 7-MCS window spills too much for that to pay.
-template <int I, int K>
-constexpr int kMinWavesPerEU = (I == 1 && K == 6) ? 4 : 1;
-
 template <int NW, int I, int K, XiMode MODE, bool HASQ>
-__global__ __launch_bounds__(NW * 64, (kMinWavesPerEU<I, K>)) void mcs_block_kernel(SweepArgs a, const uint64_t* src,
-                                                                                   uint64_t* dst, int32_t band)
+__global__ __launch_bounds__(NW * 64) void mcs_block_kernel(SweepArgs a, const uint64_t* src, uint64_t* dst,
+                                                            int32_t band)
 {
     constexpr int H = 2 * K;      // half-steps per pass
     constexpr int R = 2 * K + 1;  // window rows
@@ -305,6 +298,178 @@ __global__ __launch_bounds__(NW * 64, (kMinWavesPerEU<I, K>)) void mcs_block_ker
     }
 }
 
+// Draw-free passes of K >= kLdsDepth MCS for rows of one word per lane.  The
+// 2K+2-row register window of mcs_block_kernel no longer fits the 128 VGPRs
+// that two 512-thread workgroups per CU allow, so the two newest rows stay in
+// LDS: row s+2K, of which half-step 0 needs only the odd-sublattice y-slopes
+// (its y+ words), and row s+2K+1, which arrives by LDS DMA
+// (global_load_lds_dwordx4, no registers in flight) during step s.  Rows
+// s .. s+2K-1 live in registers; row s+2K-1 moves from LDS into the slot that
+// row s-1 left.  Three row buffers rotate: the one being filled was last read
+// before the previous step's barrier.
+constexpr int kLdsDepth = 6;
+
+// Two 512-thread workgroups per CU need at most 128 VGPRs: the 6-MCS kernel
+// fits (121); the 7- and 8-MCS kernels need more and run one workgroup per
+// CU, which suits 256-row bands on a 65536-row lattice.
+template <int NW, int K, bool HASQ>
+__global__ __launch_bounds__(NW * 64) void mcs_block_lds_kernel(SweepArgs a, const uint64_t* src, uint64_t* dst,
+                                                                int32_t band)
+{
+    constexpr int H = 2 * K;   // half-steps per pass
+    constexpr int NS = H;      // register slots: rows s .. s+2K-1
+    constexpr int WR = 64 * NW;  // words per row and array
+    static_assert(H <= 32, "exchange bits per lane");
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int y0 = (int)blockIdx.x * band, y1 = y0 + band;
+    const int ymask = a.Y - 1;
+    const int64_t P = a.plane;
+    const uint32_t wo = (uint32_t)(wv * 64 + lane);
+    const int32_t plane_bytes = (int32_t)(P * 8);
+    __amdgpu_buffer_rsrc_t rsrc[4], rdst[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        rsrc[c] = __builtin_amdgcn_make_buffer_rsrc((void*)(src + c * P), (short)0, plane_bytes, kBufferWord3);
+        rdst[c] = __builtin_amdgcn_make_buffer_rsrc((void*)(dst + c * P), (short)0, plane_bytes, kBufferWord3);
+    }
+    __shared__ __attribute__((aligned(16))) uint64_t rowbuf[3][4 * WR];  // [buffer][array][word]
+    __shared__ uint32_t xa[2][NW];
+    __shared__ uint32_t xb[2][NW];
+
+    uint64_t Wn[NS][4][1];
+    uint32_t nb0 = 0;
+    int buf = 0;
+
+    auto load_row = [&](uint64_t (&row)[4][1], int r) {
+        const int rr = r & ymask;
+        if (r >= y0 - H) {
+            const int32_t rb = (int32_t)(rr * WR * 8);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const auto v = __builtin_amdgcn_raw_buffer_load_b64(rsrc[c], (int)(wo * 8u), rb, 0);
+                row[c][0] = (uint64_t)v[0] | ((uint64_t)v[1] << 32);
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) row[c][0] = 0ull;
+        }
+    };
+    // Row r into LDS buffer b by DMA: 2*NW chunks of 128 words, two per wave,
+    // 16 bytes per lane.  Rows below y0-2K feed no half-step the band needs.
+    auto dma_row = [&](int r, int b) {
+        if (r < y0 - H) return;
+        const int64_t rr = r & ymask;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int q = wv * 2 + k;
+            const int f = 128 * q + 2 * lane;  // word of the row buffer, [array][word]
+            const uint64_t* g = src + (f / WR) * P + rr * WR + (f % WR);
+            __builtin_amdgcn_global_load_lds((const void*)g, (__attribute__((address_space(3))) void*)&rowbuf[b][128 * q],
+                                             16, 0, 0);
+        }
+    };
+    auto take_next = [&](uint32_t v) -> uint32_t { return v; };  // one word per lane: slots do not rotate
+    (void)take_next;
+
+    const int s0 = y0 - 2 * H + 1;
+
+    // Step s = s0 + k holds row s+j in register slot (u+j) mod 2K, u = k mod 2K,
+    // for j < 2K; row s+2K is in LDS buffer (k+2K) mod 3.  Shifted iff s is
+    // even, i.e. iff u is odd (s0 is odd and 2K is even).
+    auto step = [&](auto U, int s) {
+        constexpr int u = decltype(U)::value;
+        if (s >= y1) return;
+        const int k = s - s0;
+        auto sl = [](int j) { return (u + j) % NS; };
+        const int bN = (k + H) % 3;  // buffer of row s+2K
+        if (k > 0) {
+            const int bP = (k + H - 1) % 3;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) Wn[sl(H - 1)][c][0] = rowbuf[bP][c * WR + wo];
+        }
+        if (s + 1 < y1) dma_row(s + 1 + H, (k + H + 1) % 3);
+        constexpr bool shifted = (u & 1) != 0;
+        uint32_t msb_all = 0;
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            const int j = H - 1 - h;
+            const int r = s + j;
+            const int par = h & 1;
+            if (r < y0 - H + h) continue;
+            const int rr = r & ymask;
+            SweepArgs ah = a;
+            ah.parity = par;
+            ah.t = a.t + (uint32_t)(h >> 1);
+            uint64_t mp0 = 0, mq0 = 0;
+            const uint32_t nbits = nb0 >> h;
+            if (j + 1 < H) {
+                window_halfstep<shifted, WR, 1, XiMode::Fixed, HASQ>(ah, rr, (int)wo, Wn[sl(j)][par], Wn[sl(j)][2 + par],
+                                                                     Wn[sl(j + 1)][2 + (1 - par)], Wn[sl(j)][1 - par],
+                                                                     nbits, msb_all, h, mp0, mq0);
+            } else {
+                // y+ words from the newest row, in LDS; written back for the next step
+                uint64_t C[1] = {rowbuf[bN][(2 + (1 - par)) * WR + wo]};
+                window_halfstep<shifted, WR, 1, XiMode::Fixed, HASQ>(ah, rr, (int)wo, Wn[sl(j)][par], Wn[sl(j)][2 + par],
+                                                                     C, Wn[sl(j)][1 - par], nbits, msb_all, h, mp0, mq0);
+                rowbuf[bN][(2 + (1 - par)) * WR + wo] = C[0];
+            }
+            if (par == 0 && rr == 0 && r >= y0 && r < y1 && wo == 0) {
+                const int64_t dh = 2 * (int64_t)(mp0 & 1ull) - 2 * (int64_t)(mq0 & 1ull);
+                if (dh != 0) *a.h0 += dh;
+            }
+        }
+        {
+            uint32_t v = 0;
+            if (!shifted) {
+                v = (uint32_t)(rowbuf[bN][1 * WR + wo] & 1ull);  // h = 0: row s+2K, odd x-slopes
+#pragma unroll
+                for (int h = 1; h < H; ++h) v |= (uint32_t)(Wn[sl(H - h)][1 - (h & 1)][0] & 1ull) << h;
+            }
+            uint32_t pm, nv;
+            if (NW > 1) {
+                if (lane == 0) xa[buf][wv] = v;
+                if (lane == 63) xb[buf][wv] = msb_all;
+                __syncthreads();
+                pm = (lane == 0) ? xb[buf][(wv + NW - 1) % NW] : 0u;
+                nv = (lane == 63) ? xa[buf][(wv + 1) % NW] : 0u;
+                buf ^= 1;
+            } else {
+                __syncthreads();  // the row DMA'd this step is complete before it is read
+                pm = (uint32_t)__builtin_amdgcn_readlane((int)msb_all, 63);
+                nv = (uint32_t)__builtin_amdgcn_readlane((int)v, 0);
+            }
+            if (shifted && lane == 0) {
+#pragma unroll
+                for (int h = 0; h < H; ++h) {
+                    const int j = H - 1 - h;
+                    const int par = h & 1;
+                    Wn[sl(j)][1 - par][0] ^= (uint64_t)((pm >> h) & 1u);
+                }
+            }
+            if (lane == 63) nb0 = nv;
+        }
+        if (s >= y0) {
+            const int rr = s & ymask;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const uint64_t w = Wn[sl(0)][c][0];
+                __attribute__((ext_vector_type(2))) uint32_t v;
+                v[0] = (uint32_t)w;
+                v[1] = (uint32_t)(w >> 32);
+                __builtin_amdgcn_raw_buffer_store_b64(v, rdst[c], (int)(wo * 8u), (int32_t)(rr * WR * 8), 0);
+            }
+        }
+    };
+
+    // prologue: rows s0 .. s0+2K-1 into registers, row s0+2K into LDS
+#pragma unroll
+    for (int j = 0; j < H; ++j) load_row(Wn[j], s0 + j);
+    dma_row(s0 + H, H % 3);
+    __syncthreads();
+    for (int s = s0; s < y1; s += NS) unrolled_steps(step, s, std::make_integer_sequence<int, NS>{});
+}
+
 template <int NW, int I, int K>
 hipError_t launch_block(const SweepArgs& a, XiMode mode, bool has_q, const uint64_t* src, uint64_t* dst,
                         int32_t band, hipStream_t stream)
@@ -312,8 +477,13 @@ hipError_t launch_block(const SweepArgs& a, XiMode mode, bool has_q, const uint6
     const dim3 grid((unsigned)(a.Y / band));
     const dim3 block(NW * 64);
     if (mode == XiMode::Mask && a.ndraw == 0) {
-        if (has_q) hipLaunchKernelGGL((mcs_block_kernel<NW, I, K, XiMode::Fixed, true>), grid, block, 0, stream, a, src, dst, band);
-        else hipLaunchKernelGGL((mcs_block_kernel<NW, I, K, XiMode::Fixed, false>), grid, block, 0, stream, a, src, dst, band);
+        if constexpr (I == 1 && K >= kLdsDepth) {
+            if (has_q) hipLaunchKernelGGL((mcs_block_lds_kernel<NW, K, true>), grid, block, 0, stream, a, src, dst, band);
+            else hipLaunchKernelGGL((mcs_block_lds_kernel<NW, K, false>), grid, block, 0, stream, a, src, dst, band);
+        } else {
+            if (has_q) hipLaunchKernelGGL((mcs_block_kernel<NW, I, K, XiMode::Fixed, true>), grid, block, 0, stream, a, src, dst, band);
+            else hipLaunchKernelGGL((mcs_block_kernel<NW, I, K, XiMode::Fixed, false>), grid, block, 0, stream, a, src, dst, band);
+        }
     } else if constexpr (K <= kMaxDepthRandom) {
         if (mode == XiMode::Mask) {
             if (has_q) hipLaunchKernelGGL((mcs_block_kernel<NW, I, K, XiMode::Mask, true>), grid, block, 0, stream, a, src, dst, band);
