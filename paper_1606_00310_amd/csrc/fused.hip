@@ -7,7 +7,16 @@ namespace sca {
 int max_fused_depth(int32_t W, bool draw_free)
 {
     if (!draw_free) return kMaxDepthRandom;
-    return W == 1024 ? kMaxDepthWide : kMaxDepthFixed;
+    if (W != 1024) return kMaxDepthFixed;
+    // 6-MCS passes at X = 2^17 run the LDS-window kernel with 1024-thread
+    // workgroups, whose three row buffers need 96 KiB of LDS
+    int dev = 0, lds = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return kMaxDepthWide;
+    }
+    return lds >= kWideLdsBytes ? kLdsDepth : kMaxDepthWide;
 }
 
 bool fused_supported(int32_t W, int64_t Y, int32_t band, int32_t depth, bool draw_free)

@@ -38,7 +38,9 @@ namespace {
 // bandwidth saved by deeper passes matters.
 constexpr int kMaxDepthRandom = 4;
 constexpr int kMaxDepthFixed = 8;
-constexpr int kMaxDepthWide = 5;  // two words per lane
+constexpr int kMaxDepthWide = 5;  // two words per lane (X = 2^17)
+// LDS of one 1024-thread workgroup of the LDS-window kernel at X = 2^17
+constexpr int kWideLdsBytes = 3 * 4 * 1024 * 8 + 4 * 16 * 4;
 
 // Word 3 of a gfx9 buffer descriptor for untyped dword accesses.
 constexpr int32_t kBufferWord3 = 0x00020000;
@@ -508,6 +510,16 @@ hipError_t launch_depth(const SweepArgs& a, XiMode mode, bool has_q, const uint6
     case 256: return launch_block<4, 1, K>(a, mode, has_q, src, dst, band, stream);
     case 512: return launch_block<8, 1, K>(a, mode, has_q, src, dst, band, stream);
     case 1024:
+        // two words per lane in the register-window kernel, or, for the
+        // LDS-window kernel, one word per lane of a 1024-thread workgroup
+        if constexpr (K == kLdsDepth) {
+            if (mode == XiMode::Mask && a.ndraw == 0) {
+                const dim3 grid((unsigned)(a.Y / band)), block(1024);
+                if (has_q) hipLaunchKernelGGL((mcs_block_lds_kernel<16, K, true>), grid, block, 0, stream, a, src, dst, band);
+                else hipLaunchKernelGGL((mcs_block_lds_kernel<16, K, false>), grid, block, 0, stream, a, src, dst, band);
+                return hipGetLastError();
+            }
+        }
         if constexpr (K <= kMaxDepthWide) return launch_block<8, 2, K>(a, mode, has_q, src, dst, band, stream);
         else return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
