@@ -142,9 +142,9 @@ int sca_get_meta(sca_ctx* ctx, int64_t* t, int64_t* h0);
  * 256 (p, q in {0, 1}) or 128, then 64, 32, 16, 8, that leaves
  * enough workgroups to fill the chip).
  * Passes run at most 8 MCS deep when p and q are both 0 or 1 (no random
- * words; at most 5 for X = 2^17), and at most 4 deep otherwise: a larger
+ * words; at most 6 for X = 2^17), and at most 4 deep otherwise: a larger
  * depth is lowered to that limit when sca_step runs.  The automatic depth
- * without random words is 8 on bands of >= 128 rows (5 at X = 2^17) and 5 on
+ * without random words is 8 on bands of >= 128 rows (6 at X = 2^17) and 5 on
  * 64-row bands; with random words 3 on bands of >= 32 rows; 2 on 16-row
  * bands and 1 on smaller ones; the per-site path (non-dyadic p or q), which
  * is ALU-bound, is never fused.  Any setting gives bit-identical results. */

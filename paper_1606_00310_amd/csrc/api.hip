@@ -261,10 +261,10 @@ int sca_step_ex(sca_ctx* c, int64_t n_mcs, double p, double q, unsigned flags)
     // per-site path is ALU-bound and runs unfused.
     const int64_t nw = c->W >= 512 ? 8 : (c->W >= 64 ? c->W / 64 : 1);
     // Without random words (p, q in {0, 1}) a pass is bandwidth-bound and
-    // deeper passes cost little more than shallow ones: rows of one word per
-    // lane (X <= 2^16) take the LDS-window kernel at 8 MCS (5 at X = 2^17) on
-    // bands of up to 256 rows (about one 512-thread workgroup per CU); passes
-    // with draws are ALU-bound and do best at 3 MCS on bands of up to 128 rows.
+    // deeper passes cost little more than shallow ones: the LDS-window kernel
+    // runs 8 MCS (6 at X = 2^17, where it takes 1024-thread workgroups) on
+    // bands of up to 256 rows (about one workgroup per CU); passes with draws
+    // are ALU-bound and do best at 3 MCS on bands of up to 128 rows.
     const bool draw_free = !persite && a.ndraw == 0;
     int32_t band = c->band;
     if (band == 0) {
