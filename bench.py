@@ -250,7 +250,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched ensemble and serving runs")
     ap.add_argument("--ensemble-only", action="store_true", help="only the batched ensemble (for profiling)")
-    ap.add_argument("--only", choices=["random", "persite", "wide"],
+    ap.add_argument("--only", choices=["random", "half", "persite", "wide"],
                     help="time one secondary path for --steps MCS and print it (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (torch copy_) three times, the known-size "
@@ -265,7 +265,7 @@ def main():
 
     _ensure_built()
     import paper_1606_00310_amd as P
-    from paper_1606_00310_amd.inputs import HEADLINE, HEADLINE_RANDOM, PERSITE, WIDE
+    from paper_1606_00310_amd.inputs import HEADLINE, HEADLINE_HALF, HEADLINE_RANDOM, PERSITE, WIDE
 
     if args.copy_calibration:
         src = torch.ones(2**30 // 8, dtype=torch.int64, device="cuda")
@@ -277,9 +277,7 @@ def main():
         torch.cuda.empty_cache()
 
     if args.only:
-        from paper_1606_00310_amd.inputs import HEADLINE_RANDOM, PERSITE, WIDE
-
-        wk = {"random": HEADLINE_RANDOM, "persite": PERSITE, "wide": WIDE}[args.only]
+        wk = {"random": HEADLINE_RANDOM, "half": HEADLINE_HALF, "persite": PERSITE, "wide": WIDE}[args.only]
         pms = time_path(torch, P, wk.X, wk.Y, wk.p, wk.q, wk.seed, args.steps, args.warmup)
         print(json.dumps({"path": wk.name, "steps": args.steps, "ms": pms,
                           "value": wk.sites * args.steps / (pms / 1e3)}), flush=True)
@@ -335,7 +333,8 @@ def main():
 
     if not args.no_paths:
         paths = {}
-        for wk, steps, ps in ((HEADLINE_RANDOM, 198, False), (PERSITE, 100, False), (WIDE, 60, False)):
+        for wk, steps, ps in ((HEADLINE_HALF, 200, False), (HEADLINE_RANDOM, 200, False), (PERSITE, 100, False),
+                              (WIDE, 60, False)):
             pms = time_path(torch, P, wk.X, wk.Y, wk.p, wk.q, wk.seed, steps, 5, ps)
             rate = wk.sites * steps / (pms / 1e3)
             paths[wk.name] = {"value": rate, "unit": "site updates/s", "steps": steps,
@@ -344,7 +343,7 @@ def main():
         # against 256 CUs x 64 lanes x 2.4 GHz of 32-bit VALU issue with the
         # VALU instructions per site update that rocprofv3's SQ_INSTS_VALU
         # counted for the same kernel build (profiles/valu_random_paths_*).
-        for tag, wk in (("persite", PERSITE), ("random", HEADLINE_RANDOM)):
+        for tag, wk in (("persite", PERSITE), ("random", HEADLINE_RANDOM), ("half", HEADLINE_HALF)):
             per_update = _valu_per_update(tag)
             pv = paths[wk.name]
             pv["roofline"] = None if per_update is None else {

@@ -145,9 +145,10 @@ int sca_get_meta(sca_ctx* ctx, int64_t* t, int64_t* h0);
  * words; at most 6 for X = 2^17), and at most 4 deep otherwise: a larger
  * depth is lowered to that limit when sca_step runs.  The automatic depth
  * without random words is 8 on bands of >= 128 rows (6 at X = 2^17) and 5 on
- * 64-row bands; with random words 3 on bands of >= 32 rows; 2 on 16-row
- * bands and 1 on smaller ones; the per-site path (non-dyadic p or q), which
- * is ALU-bound, is never fused.  Any setting gives bit-identical results. */
+ * 64-row bands; with random words 4 on bands of >= 128 rows and 3 on 32- and
+ * 64-row bands; 2 on 16-row bands and 1 on smaller ones; the per-site path
+ * (non-dyadic p or q), which is ALU-bound, is never fused.  Any setting gives
+ * bit-identical results. */
 int sca_set_blocking(sca_ctx* ctx, int32_t depth, int32_t band);
 
 /* Sets the MCS counter (for resuming from a saved state; the caller restores

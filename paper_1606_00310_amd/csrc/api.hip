@@ -264,7 +264,7 @@ int sca_step_ex(sca_ctx* c, int64_t n_mcs, double p, double q, unsigned flags)
     // deeper passes cost little more than shallow ones: the LDS-window kernel
     // runs 8 MCS (6 at X = 2^17, where it takes 1024-thread workgroups) on
     // bands of up to 256 rows (about one workgroup per CU); passes with draws
-    // are ALU-bound and do best at 3 MCS on bands of up to 128 rows.
+    // are ALU-bound and do best at 4 MCS on bands of up to 128 rows.
     const bool draw_free = !persite && a.ndraw == 0;
     int32_t band = c->band;
     if (band == 0) {
@@ -272,11 +272,11 @@ int sca_step_ex(sca_ctx* c, int64_t n_mcs, double p, double q, unsigned flags)
         while (b > 8 && c->Y / b < 2048 / nw) b >>= 1;
         band = (int32_t)b;
     }
-    const int32_t dmax = sca::max_fused_depth(c->W, draw_free);
+    const int32_t dmax = sca::max_fused_depth(c->W, mode, a.ndraw);
     int32_t depth = c->depth;
     if (depth < 0) {
         depth = persite ? 0
-                        : band >= 128 ? (draw_free ? 8 : 3)
+                        : band >= 128 ? (draw_free ? 8 : 4)
                         : band >= 64 ? (draw_free ? 5 : 3)
                         : band >= 32 ? 3
                         : band >= 16 ? 2
@@ -286,7 +286,7 @@ int sca_step_ex(sca_ctx* c, int64_t n_mcs, double p, double q, unsigned flags)
         depth = dmax;
     }
     bool fuse = !(flags & SCA_NO_FUSE) && depth > 0 && n_mcs >= 2 &&
-                sca::fused_supported(c->W, c->Y, band, depth, draw_free);
+                sca::fused_supported(c->W, c->Y, band, depth, mode, a.ndraw);
     if (fuse && !c->alt) {
         if (hipMalloc(&c->alt, sizeof(uint64_t) * (size_t)(4 * c->Y * c->W)) != hipSuccess) {
             (void)hipGetLastError();

@@ -4,9 +4,11 @@
 
 namespace sca {
 
-int max_fused_depth(int32_t W, bool draw_free)
+int max_fused_depth(int32_t W, XiMode mode, int32_t ndraw)
 {
-    if (!draw_free) return kMaxDepthRandom;
+    if (mode == XiMode::PerSite) return kMaxDepthPerSite;
+    if (mode != XiMode::Mask) return 0;
+    if (ndraw > 0) return kMaxDepthMask;
     if (W != 1024) return kMaxDepthFixed;
     // 6-MCS passes at X = 2^17 run the LDS-window kernel with 1024-thread
     // workgroups, whose three row buffers need 96 KiB of LDS
@@ -19,18 +21,17 @@ int max_fused_depth(int32_t W, bool draw_free)
     return lds >= kWideLdsBytes ? kLdsDepth : kMaxDepthWide;
 }
 
-bool fused_supported(int32_t W, int64_t Y, int32_t band, int32_t depth, bool draw_free)
+bool fused_supported(int32_t W, int64_t Y, int32_t band, int32_t depth, XiMode mode, int32_t ndraw)
 {
     return (W == 64 || W == 128 || W == 256 || W == 512 || W == 1024) && depth >= 1 &&
-           depth <= max_fused_depth(W, draw_free) && band >= 4 && (band & (band - 1)) == 0 && (Y % band) == 0 &&
+           depth <= max_fused_depth(W, mode, ndraw) && band >= 4 && (band & (band - 1)) == 0 && (Y % band) == 0 &&
            Y >= 2 * band && band >= 2 * depth;
 }
 
 hipError_t launch_mcs_fused(const SweepArgs& a, XiMode mode, bool has_q, const uint64_t* src, uint64_t* dst,
                             int32_t band, int32_t depth, hipStream_t stream)
 {
-    const bool draw_free = mode == XiMode::Mask && a.ndraw == 0;
-    if (!fused_supported(a.W, a.Y, band, depth, draw_free) || mode == XiMode::Inject) return hipErrorInvalidValue;
+    if (!fused_supported(a.W, a.Y, band, depth, mode, a.ndraw)) return hipErrorInvalidValue;
     switch (depth) {
     case 1: return launch_depth<1>(a, mode, has_q, src, dst, band, stream);
     case 2: return launch_depth<2>(a, mode, has_q, src, dst, band, stream);

@@ -33,10 +33,11 @@
 namespace sca {
 namespace {
 
-// Deepest pass per kind of launch: the window of 2K+2 rows lives in
-// registers, and passes with random draws are ALU-bound well before the
-// bandwidth saved by deeper passes matters.
-constexpr int kMaxDepthRandom = 4;
+// Deepest pass per kind of launch: passes with random draws are ALU-bound
+// before the bandwidth saved by deeper passes matters, and the per-site
+// path's step body is too large to unroll.
+constexpr int kMaxDepthMask = 4;
+constexpr int kMaxDepthPerSite = 4;
 constexpr int kMaxDepthFixed = 8;
 constexpr int kMaxDepthWide = 5;  // two words per lane (X = 2^17)
 // LDS of one 1024-thread workgroup of the LDS-window kernel at X = 2^17
@@ -110,11 +111,12 @@ __global__ __launch_bounds__(NW * 64) void mcs_block_kernel(SweepArgs a, const u
     constexpr int H = 2 * K;      // half-steps per pass
     constexpr int R = 2 * K + 1;  // window rows
     constexpr int NS = R + 1;     // register slots: the window and the row in flight
-    // Without per-site compares the step body is small: the sweep is unrolled
-    // NS steps deep so that the window rotates through the slots instead of
-    // being moved down one slot per step, and each unrolled step knows at
-    // compile time whether its rows are shifted.
-    constexpr bool ROT = MODE == XiMode::Fixed;
+    // Without per-site compares the step body is small enough to unroll the
+    // sweep NS steps deep, so that the window rotates through the slots
+    // instead of being moved down one slot per step (which also frees the
+    // registers the moves needed), and each unrolled step knows at compile
+    // time whether its rows are shifted.
+    constexpr bool ROT = MODE != XiMode::PerSite;
     static_assert(H * I <= 32, "exchange bits per lane");
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -486,16 +488,20 @@ hipError_t launch_block(const SweepArgs& a, XiMode mode, bool has_q, const uint6
             if (has_q) hipLaunchKernelGGL((mcs_block_kernel<NW, I, K, XiMode::Fixed, true>), grid, block, 0, stream, a, src, dst, band);
             else hipLaunchKernelGGL((mcs_block_kernel<NW, I, K, XiMode::Fixed, false>), grid, block, 0, stream, a, src, dst, band);
         }
-    } else if constexpr (K <= kMaxDepthRandom) {
-        if (mode == XiMode::Mask) {
+    } else if (mode == XiMode::Mask) {
+        if constexpr (K <= kMaxDepthMask) {
             if (has_q) hipLaunchKernelGGL((mcs_block_kernel<NW, I, K, XiMode::Mask, true>), grid, block, 0, stream, a, src, dst, band);
             else hipLaunchKernelGGL((mcs_block_kernel<NW, I, K, XiMode::Mask, false>), grid, block, 0, stream, a, src, dst, band);
         } else {
-            if (has_q) hipLaunchKernelGGL((mcs_block_kernel<NW, I, K, XiMode::PerSite, true>), grid, block, 0, stream, a, src, dst, band);
-            else hipLaunchKernelGGL((mcs_block_kernel<NW, I, K, XiMode::PerSite, false>), grid, block, 0, stream, a, src, dst, band);
+            return hipErrorInvalidValue;
         }
     } else {
-        return hipErrorInvalidValue;
+        if constexpr (K <= kMaxDepthPerSite) {
+            if (has_q) hipLaunchKernelGGL((mcs_block_kernel<NW, I, K, XiMode::PerSite, true>), grid, block, 0, stream, a, src, dst, band);
+            else hipLaunchKernelGGL((mcs_block_kernel<NW, I, K, XiMode::PerSite, false>), grid, block, 0, stream, a, src, dst, band);
+        } else {
+            return hipErrorInvalidValue;
+        }
     }
     return hipGetLastError();
 }

@@ -13,9 +13,11 @@ hipError_t launch_halfstep(const SweepArgs& a, XiMode mode, bool has_q, hipStrea
 
 // `depth` MCS (2*depth half-steps from MCS a.t on) in one pass, reading src
 // and writing dst (both S[2][2][Y][W]); one workgroup per band of `band` rows.
-// draw_free: p and q in {0, 1} (no random words), which allows deeper passes.
-int max_fused_depth(int32_t W, bool draw_free);
-bool fused_supported(int32_t W, int64_t Y, int32_t band, int32_t depth, bool draw_free);
+// The deepest pass depends on the kind of acceptance words: mode and, in
+// mask mode, the number of draws (0: p and q in {0, 1}, which allows the
+// deepest passes).
+int max_fused_depth(int32_t W, XiMode mode, int32_t ndraw);
+bool fused_supported(int32_t W, int64_t Y, int32_t band, int32_t depth, XiMode mode, int32_t ndraw);
 hipError_t launch_mcs_fused(const SweepArgs& a, XiMode mode, bool has_q, const uint64_t* src, uint64_t* dst,
                             int32_t band, int32_t depth, hipStream_t stream);
 

@@ -35,6 +35,9 @@ MEDIUM = Workload("octahedron-4096x4096-p0.75-q0.25", 4096, 4096, 0.75, 0.25, 10
 # calls per word).
 HEADLINE = Workload("octahedron-65536x65536-p1-q0", 65536, 65536, 1.0, 0.0, 2000, 42)
 HEADLINE_RANDOM = Workload("octahedron-65536x65536-p0.9375-q0", 65536, 65536, 0.9375, 0.0, 2000, 42)
+# The paper's own throughput workload (Sec. III): 2^16 x 2^16 at p = 1/2
+# (one 64-bit draw per word, half a Philox call).
+HEADLINE_HALF = Workload("octahedron-65536x65536-p0.5-q0", 65536, 65536, 0.5, 0.0, 2000, 42)
 # Lateral size 2^17 (the paper's cyan bar, Sec. III): 4 GiB of packed slopes.
 WIDE = Workload("octahedron-131072x131072-p1-q0", 131072, 131072, 1.0, 0.0, 2000, 42)
 # Arbitrary probabilities: one 32-bit uniform per site.
