@@ -16,11 +16,20 @@
 // instead of per half-step).  Same-parity sites share no bond, so within a
 // half-step every word is read and written by exactly one lane; the barrier
 // between half-steps (a workgroup-scope release/acquire) orders them.
+#include <utility>
+
 #include "halfstep.hpp"
 #include "sca_internal.hpp"
 
 namespace sca {
 namespace {
+
+// Calls f(integral_constant<u>, k + u) for u = 0 .. sizeof...(U)-1.
+template <class F, int... U>
+__device__ __forceinline__ void unrolled_steps(F& f, int k, std::integer_sequence<int, U...>)
+{
+    (f(std::integral_constant<int, U>{}, k + U), ...);
+}
 
 // Word 3 of a gfx9 buffer descriptor for untyped dword accesses.
 constexpr int32_t kBufferWord3 = 0x00020000;
@@ -161,11 +170,20 @@ __device__ __forceinline__ void blocked_passes(SweepArgs a, uint64_t* S, uint64_
             for (int j = 0; j < R; ++j) load_row(Wn[j], j - 2 * H + 1);
         }
         const int nsteps = bh + 2 * H - 1;  // the same for every group: uniform barriers
-        for (int k = 0; k < nsteps; ++k) {
+        // Step k holds relative row q+j (q = k-2H+1) in slot (u+j) mod NS,
+        // u = k mod NS: the sweep is unrolled NS steps deep so that the window
+        // rotates through the slots instead of being moved, and a step's rows
+        // are shifted iff k is odd (the band start is even), known at compile
+        // time in the unrolled steps.
+        auto step = [&](auto U, int k) {
+            constexpr int u = decltype(U)::value;
+            if (k >= nsteps) return;
             if (k == 2 * H) __syncthreads();  // every band is done with its upper halo
-            if (!active) continue;
+            if (!active) return;
+            auto sl = [](int j) { return (u + j) % NS; };
+            constexpr bool shifted = (u & 1) != 0;
             const int q = k - 2 * H + 1;      // this step's first window row, relative to y0
-            if (q + 1 < bh) load_row(Wn[R], q + 1 + H);
+            if (q + 1 < bh) load_row(Wn[sl(H + 1)], q + 1 + H);
 #pragma unroll
             for (int h = 0; h < H; ++h) {
                 const int j = H - 1 - h;
@@ -173,21 +191,28 @@ __device__ __forceinline__ void blocked_passes(SweepArgs a, uint64_t* S, uint64_
                 const int par = h & 1;
                 if (rel < -H + h) continue;
                 const int rr = (y0 + rel) & ymask;
-                const bool shifted = ((par ^ (rel & 1)) != 0);  // y0 is even
                 SweepArgs ah = a;
                 ah.parity = par;
                 ah.t = a.t + (uint32_t)(h >> 1);
                 // the row is one word per lane: the next word's bit 0 and the
                 // previous word's top mask bit come from the neighbouring lanes of
                 // the group, wrapping at the row end
-                uint64_t(&D)[1] = Wn[j][1 - par];
+                uint64_t(&D)[1] = Wn[sl(j)][1 - par];
                 uint64_t XP[1], M[1], mp0 = 0, mq0 = 0;
-                const uint32_t nxt = (uint32_t)__shfl((int)(uint32_t)(D[0] & 1ull), nxl);
-                XP[0] = shifted ? ((D[0] >> 1) | ((uint64_t)nxt << 63)) : D[0];
-                row_masks<1, 1, XiMode::Mask, HASQ>(ah, rr, gl, Wn[j][par], Wn[j][2 + par], Wn[j + 1][2 + (1 - par)],
-                                                     XP, M, mp0, mq0);
-                const uint32_t prv = (uint32_t)__shfl((int)(uint32_t)(M[0] >> 63), pvl);
-                D[0] ^= shifted ? ((M[0] << 1) | (uint64_t)prv) : M[0];
+                if constexpr (shifted) {
+                    const uint32_t nxt = (uint32_t)__shfl((int)(uint32_t)(D[0] & 1ull), nxl);
+                    XP[0] = (D[0] >> 1) | ((uint64_t)nxt << 63);
+                } else {
+                    XP[0] = D[0];
+                }
+                row_masks<1, 1, XiMode::Mask, HASQ>(ah, rr, gl, Wn[sl(j)][par], Wn[sl(j)][2 + par],
+                                                     Wn[sl(j + 1)][2 + (1 - par)], XP, M, mp0, mq0);
+                if constexpr (shifted) {
+                    const uint32_t prv = (uint32_t)__shfl((int)(uint32_t)(M[0] >> 63), pvl);
+                    D[0] ^= (M[0] << 1) | (uint64_t)prv;
+                } else {
+                    D[0] ^= M[0];
+                }
                 if (par == 0 && rel == 0 && g == 0 && gl == 0) {  // site (0,0)
                     const int64_t dh = 2 * (int64_t)(mp0 & 1ull) - 2 * (int64_t)(mq0 & 1ull);
                     if (dh != 0) *a.h0 += dh;
@@ -195,13 +220,10 @@ __device__ __forceinline__ void blocked_passes(SweepArgs a, uint64_t* S, uint64_
             }
             if (q >= 0) {
 #pragma unroll
-                for (int c = 0; c < 4; ++c) st(rs[c], soff(y0 + q), Wn[0][c][0]);
+                for (int c = 0; c < 4; ++c) st(rs[c], soff(y0 + q), Wn[sl(0)][c][0]);
             }
-#pragma unroll
-            for (int j = 0; j < NS - 1; ++j)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) Wn[j][c][0] = Wn[j + 1][c][0];
-        }
+        };
+        for (int k = 0; k < nsteps; k += NS) unrolled_steps(step, k, std::make_integer_sequence<int, NS>{});
         __syncthreads();
     }
 }

@@ -373,9 +373,6 @@ __global__ __launch_bounds__(NW * 64) void mcs_block_lds_kernel(SweepArgs a, con
                                              16, 0, 0);
         }
     };
-    auto take_next = [&](uint32_t v) -> uint32_t { return v; };  // one word per lane: slots do not rotate
-    (void)take_next;
-
     const int s0 = y0 - 2 * H + 1;
 
     // Step s = s0 + k holds row s+j in register slot (u+j) mod 2K, u = k mod 2K,
