@@ -101,6 +101,68 @@ def test_headline_random_windows(orc, sca):
     lat.close()
 
 
+def test_headline_half_windows(orc, sca):
+    """2^16 x 2^16 at p = 1/2, the paper's own throughput workload: windows
+    after 13 MCS (blocked passes of 4 MCS and a remainder split in two)."""
+    from paper_1606_00310_amd.inputs import HEADLINE_HALF as w
+
+    T = 13
+    _say("[fullsize] 65536^2 p=0.5 windows")
+    lat = sca.Lattice(w.X, w.Y, seed=w.seed)
+    lat.step(T, w.p, w.q)
+    check_windows(orc, lat, T, w.p, w.q, w.seed, [(0, 0), (w.X - 30, 255), (40000, 65500)])
+    assert lat.meta()[1] == int(lat.heights(0, 1)[0, 0])
+    lat.close()
+
+
+def test_headline_p1_odd_length_windows(orc, sca):
+    """p = 1 for 21 MCS (two 8-MCS passes of the LDS-window kernel and a
+    5-MCS remainder as passes of 3 and 2) must give the closed form; then
+    p = 1, q = 1/2 for 3 more MCS, whose windows the oracle computes from the
+    closed-form state at t = 21 (flat slopes, heights raised by 42)."""
+    from paper_1606_00310_amd.inputs import HEADLINE as w
+
+    _say("[fullsize] 65536^2 p=1 21 MCS, then p=1 q=0.5 3 MCS")
+    lat = sca.Lattice(w.X, w.Y, seed=w.seed)
+    lat.step(21, 1.0, 0.0)
+    assert lat.meta() == (21, 42)
+    S = lat.slopes
+    assert bool((S[:, 0] == 0).all()) and bool((S[:, 1] == -1).all())
+    T, n = 3, 40
+    lat.step(T, 1.0, 0.5)
+    m = 2 * T + 1
+    for wx, wy in [(0, 0), (w.X - 20, w.Y - 20), (31000, 255)]:
+        _say(f"  window at x={wx} y={wy}")
+        x0, y0 = (wx - m) % w.X, (wy - m) % w.Y
+        patch = orc.flat_patch(w.X, w.Y, x0, y0, n + 2 * m, n + 2 * m)
+        patch.t, patch.h0 = 21, 42
+        patch.H += 42
+        orc.run(patch, T, 1.0, 0.5, seed=w.seed)
+        got = rows_wrapped(lat, wy, n)
+        np.testing.assert_array_equal(got[:, (wx + np.arange(n)) % w.X], patch.H[m:m + n, m:m + n])
+    assert lat.meta()[0] == 24
+    lat.close()
+
+
+def test_wide_p1_closed_form(sca):
+    """2^17 x 2^17 (4 GiB of slopes), p = 1: 6-MCS passes of the LDS-window
+    kernel with 1024-thread workgroups; the closed form after 120 MCS."""
+    from paper_1606_00310_amd.inputs import WIDE as w
+
+    _say("[fullsize] 131072^2 p=1 120 MCS")
+    t = 120
+    lat = sca.Lattice(w.X, w.Y, seed=w.seed)
+    lat.step(t, w.p, w.q)
+    assert lat.meta() == (t, 2 * t)
+    S = lat.slopes
+    assert bool((S[:, 0] == 0).all()) and bool((S[:, 1] == -1).all())
+    for y0 in (0, 65535, 131070):
+        h = lat.heights(y0, 2).cpu().numpy()
+        par = (np.arange(w.X)[None, :] + (y0 + np.arange(2))[:, None]) & 1
+        np.testing.assert_array_equal(h, 2 * t + par)
+    lat.close()
+
+
 def test_headline_random_full_length_invariants(sca):
     """All 2000 MCS at p = 0.9375 on 2^16 x 2^16: sampled rows remain valid
     octahedron surfaces; moments agree with the sampled heights' bounds."""
