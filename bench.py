@@ -4,10 +4,13 @@ A step is one Monte-Carlo step (the even and the odd half-step) over the
 2^16 x 2^16 lattice (1 GiB of packed slopes, resident in HBM), p = 1, q = 0,
 seed 42, grown from the flat surface.  The metric is site updates per second
 (X * Y * steps / time), timed with HIP events on the stream the kernels run
-on.  The roofline object prices the half-step kernel against HBM bandwidth
-with its algorithmic traffic: every packed slope word is read once and
-written once per half-step, X*Y/4 bytes each way (1 byte per site update per
-MCS, the paper's bandwidth model in Sec. III).
+on.  The sweep runs as temporally blocked passes of 12 MCS; the roofline
+object prices that pass kernel against HBM bandwidth with its algorithmic
+traffic: every packed slope word is read once and written once per pass,
+X*Y/4 bytes each way (the paper's bandwidth model in Sec. III charges 1 byte
+per site update, one pass per half-step), and, beside it, against the 32-bit
+VALU issue rate with the instructions per pass that rocprofv3 counted; the
+roof the pass comes closer to is the bound.
 
 Prints one JSON line.
 """
@@ -28,7 +31,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock: 32-bit VALU lane instructions/s
-COUNTERS = os.path.join(ROOT, "profiles", "mcs_block_65536x65536_p1_counters.json")
+COUNTERS = os.path.join(ROOT, "profiles", "mcs_fixed_65536x65536_p1_counters.json")
 VALU_COUNTERS = os.path.join(ROOT, "profiles", "valu_random_paths_counters.json")
 
 
@@ -49,18 +52,19 @@ def _sha(paths):
     return h.hexdigest()
 
 
-def _traffic(bytes_per_launch_alg):
-    """Counter-measured HBM bytes per blocked-pass launch, if the counters were
-    taken on the current kernel sources."""
+def _pass_counters():
+    """rocprofv3 counters of the blocked-pass kernel (HBM bytes and VALU
+    instructions per launch), if they were taken on the current kernel
+    sources."""
     try:
         with open(COUNTERS) as f:
             c = json.load(f)
     except (OSError, ValueError):
-        return None
+        return {}
     files = [os.path.join(ROOT, s) for s in c.get("sources", [])]
     if not files or c.get("sources_sha256") != _sha(files):
-        return None
-    return c.get("hbm_bytes_per_launch")
+        return {}
+    return c
 
 
 def _valu_per_update(tag):
@@ -290,11 +294,11 @@ def main():
     w = HEADLINE
     K, Wm = args.steps, args.warmup
     # The sweep runs as temporally blocked passes of DEPTH MCS each (all
-    # sixteen half-steps of eight MCS in one sweep over the state, BAND-row
+    # 24 half-steps of twelve MCS in one sweep over the state, BAND-row
     # bands per workgroup), an even number of passes per call; the MCS left
     # over run as two shallower passes.  Every pass reads the packed state once
     # and writes it once: X*Y/4 bytes each way.
-    DEPTH, BAND = 8, 256
+    DEPTH, BAND = 12, 256
     n_pass = (K // DEPTH) & ~1
     n_fused = n_pass * DEPTH
     torch.cuda.synchronize()
@@ -308,18 +312,31 @@ def main():
     alg_bytes = w.sites // 2
     if n_pass:
         avg_ms = fused_ms / n_pass
-        kernel = f"mcs_block_lds_kernel<8,{DEPTH},false>"
+        kernel = f"mcs_fixed_kernel<8,{DEPTH},1,false>"
         per_update = alg_bytes / (w.sites * DEPTH)
     else:
         avg_ms = ms / (2 * K)
         kernel = "halfstep_kernel<64,8,Mask,false>"
         per_update = alg_bytes / w.sites
     achieved = alg_bytes / (avg_ms / 1e3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": _traffic(alg_bytes), "kernel": kernel,
-                "alg_bytes_per_launch": alg_bytes, "mcs_per_launch": DEPTH if n_pass else 0.5,
-                "alg_bytes_per_site_update": per_update, "avg_launch_ms": round(avg_ms, 5),
-                "launches_timed": n_pass if n_pass else 2 * K}
+    pc = _pass_counters() if n_pass else {}
+    hbm = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4)}
+    roofline = dict(hbm)
+    valu = pc.get("valu", {}).get("sq_insts_valu_per_launch")
+    if valu:
+        # VALU lane instructions per launch (wave instructions x 64) over the launch time
+        va = valu * 64 / (avg_ms / 1e3)
+        alu = {"bound": "alu", "achieved": va, "peak": VALU_LANE_OPS, "unit": "VALU lane instructions/s",
+               "frac": round(va / VALU_LANE_OPS, 4)}
+        if alu["frac"] > hbm["frac"]:
+            roofline = dict(alu, hbm=hbm)
+        else:
+            roofline["alu"] = alu
+    roofline.update({"traffic": pc.get("hbm_bytes_per_launch"), "kernel": kernel,
+                     "alg_bytes_per_launch": alg_bytes, "mcs_per_launch": DEPTH if n_pass else 0.5,
+                     "alg_bytes_per_site_update": per_update, "avg_launch_ms": round(avg_ms, 5),
+                     "launches_timed": n_pass if n_pass else 2 * K})
 
     out = {
         "metric": "site updates/s (bit-vectorized + arbitrary-p) vs HBM roofline; batched vs solo",
@@ -335,7 +352,9 @@ def main():
         paths = {}
         for wk, steps, ps in ((HEADLINE_HALF, 200, False), (HEADLINE_RANDOM, 200, False), (PERSITE, 100, False),
                               (WIDE, 60, False)):
-            pms = time_path(torch, P, wk.X, wk.Y, wk.p, wk.q, wk.seed, steps, 5, ps)
+            # 24 warm-up MCS: several whole passes over freshly allocated state
+            # (the first passes over a new 8 GiB lattice pair run about 10 % slower)
+            pms = time_path(torch, P, wk.X, wk.Y, wk.p, wk.q, wk.seed, steps, 24, ps)
             rate = wk.sites * steps / (pms / 1e3)
             paths[wk.name] = {"value": rate, "unit": "site updates/s", "steps": steps,
                               "hbm_frac_1B_per_update": round(rate / (HBM_PEAK_GBS * 1e9), 4)}

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsca.so")
-SOURCES = ["sweep.hip", "fused.hip", "fused_deep.hip", "measure.hip", "batch.hip", "api.hip"]
+SOURCES = ["sweep.hip", "fused.hip", "fused_deep.hip", "fused_deeper.hip", "measure.hip", "batch.hip", "api.hip"]
 ARCH = os.environ.get("SCA_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

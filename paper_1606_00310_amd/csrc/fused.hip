@@ -1,5 +1,6 @@
-// fused.hip -- dispatch of the temporally blocked passes (kernel in fused.hpp);
-// passes of 1..4 MCS are instantiated here, deeper ones in fused_deep.hip.
+// fused.hip -- dispatch of the temporally blocked passes (kernels in fused.hpp);
+// passes of 1..4 MCS are instantiated here, 5..8 in fused_deep.hip and 9..12
+// (X = 2^16) in fused_deeper.hip.
 #include "fused.hpp"
 
 namespace sca {
@@ -9,6 +10,7 @@ int max_fused_depth(int32_t W, XiMode mode, int32_t ndraw)
     if (mode == XiMode::PerSite) return kMaxDepthPerSite;
     if (mode != XiMode::Mask) return 0;
     if (ndraw > 0) return kMaxDepthMask;
+    if (W == 512) return kMaxDepthFixed512;
     if (W != 1024) return kMaxDepthFixed;
     // 6-MCS passes at X = 2^17 run the LDS-window kernel with 1024-thread
     // workgroups, whose three row buffers need 96 KiB of LDS

@@ -39,6 +39,9 @@ namespace {
 constexpr int kMaxDepthMask = 4;
 constexpr int kMaxDepthPerSite = 4;
 constexpr int kMaxDepthFixed = 8;
+// X = 2^16 (512 words per row): the register window of mcs_fixed_kernel holds
+// up to 12 MCS in one workgroup per CU.
+constexpr int kMaxDepthFixed512 = 12;
 constexpr int kMaxDepthWide = 5;  // two words per lane (X = 2^17)
 // LDS of one 1024-thread workgroup of the LDS-window kernel at X = 2^17
 constexpr int kWideLdsBytes = 3 * 4 * 1024 * 8 + 4 * 16 * 4;
@@ -51,6 +54,14 @@ template <class F, int... U>
 __device__ __forceinline__ void unrolled_steps(F& f, int s, std::integer_sequence<int, U...>)
 {
     (f(std::integral_constant<int, U>{}, s + U), ...);
+}
+
+// Calls f(integral_constant<u>, s + u) for u = 0, 1, ... while it returns
+// true; returns whether every call did.
+template <class F, int... U>
+__device__ __forceinline__ bool unrolled_steps_while(F& f, int s, std::integer_sequence<int, U...>)
+{
+    return (f(std::integral_constant<int, U>{}, s + U) && ...);
 }
 
 // Lane i receives v from lane i+1; lane 63 keeps `edge` (DPP wavefront shift).
@@ -312,6 +323,10 @@ __global__ __launch_bounds__(NW * 64) void mcs_block_kernel(SweepArgs a, const u
 // row s-1 left.  Three row buffers rotate: the one being filled was last read
 // before the previous step's barrier.
 constexpr int kLdsDepth = 6;
+// From this depth on, draw-free passes of one word per lane run one
+// workgroup per CU anyway, and the register window with loads three steps
+// ahead (mcs_fixed_kernel) replaces the LDS window.
+constexpr int kFixedDeepDepth = 7;
 
 // Two 512-thread workgroups per CU need at most 128 VGPRs: the 6-MCS kernel
 // fits (121); the 7- and 8-MCS kernels need more and run one workgroup per
@@ -471,6 +486,216 @@ __global__ __launch_bounds__(NW * 64) void mcs_block_lds_kernel(SweepArgs a, con
     for (int s = s0; s < y1; s += NS) unrolled_steps(step, s, std::make_integer_sequence<int, NS>{});
 }
 
+// One draw-free half-step (p, q in {0, 1}) of a window row held as 32-bit
+// halves: A, B on-site x- and y- slopes, C the y+ slopes, D the x+ slopes
+// (aligned, or one site further when SH).  Without q the pass has p = 1, so
+// the update mask is T & C with T = ~A & ~B & x+ (Eq. (3) with every draw
+// accepted), and each slope it flips is x ^ (T & C): one v_bitop3 per half
+// word (truth table 0x78) instead of forming the mask and xor-ing it in.
+// edge: lane 63's next-word bit in bit 0; msb collects the top mask bit of
+// shifted rows (shifted in from the right); mp_lo, mq_lo: low mask words.
+template <bool SH, bool HASQ>
+__device__ __forceinline__ void fixed_halfstep(uint32_t (&A)[2], uint32_t (&B)[2], uint32_t (&C)[2],
+                                               uint32_t (&D)[2], uint32_t edge, uint32_t xip, uint32_t xiq,
+                                               uint32_t& msb, uint32_t& mp_lo, uint32_t& mq_lo)
+{
+    uint32_t XP[2];
+    if constexpr (SH) {
+        const uint32_t nl = from_next_lane_or(D[0], edge);
+        XP[0] = __builtin_amdgcn_alignbit(D[1], D[0], 1u);
+        XP[1] = __builtin_amdgcn_alignbit(nl, D[1], 1u);
+    } else {
+        XP[0] = D[0];
+        XP[1] = D[1];
+    }
+    uint32_t M[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        if constexpr (!HASQ) {
+            const uint32_t T = __builtin_amdgcn_bitop3_b32(A[i], B[i], XP[i], 0x02);  // ~A & ~B & x+
+            M[i] = T & C[i];
+            A[i] = __builtin_amdgcn_bitop3_b32(A[i], T, C[i], 0x78);  // A ^ (T & C)
+            B[i] = __builtin_amdgcn_bitop3_b32(B[i], T, C[i], 0x78);
+            if constexpr (!SH) D[i] = __builtin_amdgcn_bitop3_b32(D[i], T, C[i], 0x78);
+            C[i] = __builtin_amdgcn_bitop3_b32(C[i], T, C[i], 0x78);
+            if (i == 0) { mp_lo = M[0]; mq_lo = 0; }
+        } else {
+            const uint32_t mp = __builtin_amdgcn_bitop3_b32(__builtin_amdgcn_bitop3_b32(A[i], B[i], XP[i], 0x02), C[i],
+                                                            xip, 0x80);  // xi & ~A & ~B & x+ & C
+            const uint32_t mq = __builtin_amdgcn_bitop3_b32(__builtin_amdgcn_bitop3_b32(A[i], B[i], XP[i], 0x40), C[i],
+                                                            xiq, 0x20);  // xi & A & B & ~x+ & ~C
+            M[i] = mp | mq;
+            A[i] ^= M[i];
+            B[i] ^= M[i];
+            C[i] ^= M[i];
+            if constexpr (!SH) D[i] ^= M[i];
+            if (i == 0) { mp_lo = mp; mq_lo = mq; }
+        }
+    }
+    if constexpr (SH) {
+        const uint32_t ph = from_prev_lane_or_zero(M[1]);  // bit 31: the previous word's top mask bit
+        D[0] ^= __builtin_amdgcn_alignbit(M[0], ph, 31u);
+        D[1] ^= __builtin_amdgcn_alignbit(M[1], M[0], 31u);
+        msb = __builtin_amdgcn_alignbit(msb, M[1], 31u);  // (msb << 1) | top bit
+    }
+    // Pin the new slopes here: left alone, the compiler sinks each update to
+    // the next step, where the words are read again, and keeps the masks of
+    // all 2K half-steps live until then (about 50 more VGPRs at K = 8).
+    asm volatile("" : "+v"(A[0]), "+v"(A[1]), "+v"(B[0]), "+v"(B[1]), "+v"(C[0]), "+v"(C[1]), "+v"(D[0]), "+v"(D[1]));
+}
+
+// Deep draw-free passes for rows of one word per lane (X = 2^13 .. 2^16)
+// with one workgroup per CU: the register window of 2K+1 rows plus DIST
+// rows in flight, loaded DIST steps ahead of use so that each load has
+// DIST row steps of compute to arrive in (3; at K = 12 the window alone
+// fills the registers and a step of 24 half-steps hides a load by itself).
+// Without LDS DMA the one barrier per step waits only for LDS, not for loads
+// or stores.  The first two unrolled rounds of the sweep, which hold the
+// band's upper halo, the origin row of band 0 and the rows not yet stored,
+// are compiled with those conditions resolved per step; the rest runs with
+// no per-half-step conditions.
+template <int NW, int K, int DIST, bool HASQ>
+__global__ __launch_bounds__(NW * 64) void mcs_fixed_kernel(SweepArgs a, const uint64_t* src, uint64_t* dst,
+                                                            int32_t band)
+{
+    constexpr int H = 2 * K;             // half-steps per pass
+    constexpr int NS = H + 1 + DIST;     // register slots: window and rows in flight
+    constexpr int WR = 64 * NW;          // words per row and array
+    static_assert(NS % 2 == 0, "even rotation keeps each step's alignment fixed");
+    static_assert(H <= 32, "exchange bits per lane");
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int y0 = (int)blockIdx.x * band, y1 = y0 + band;
+    const int ymask = a.Y - 1;
+    const int64_t P = a.plane;
+    const uint32_t voff = (uint32_t)(wv * 64 + lane) * 8u;
+    const int32_t plane_bytes = (int32_t)(P * 8);
+    __amdgpu_buffer_rsrc_t rsrc[4], rdst[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        rsrc[c] = __builtin_amdgcn_make_buffer_rsrc((void*)(src + c * P), (short)0, plane_bytes, kBufferWord3);
+        rdst[c] = __builtin_amdgcn_make_buffer_rsrc((void*)(dst + c * P), (short)0, plane_bytes, kBufferWord3);
+    }
+    __shared__ uint32_t xa[2][NW];  // lane 0: bit 0 of the x+ words of the next step's half-steps
+    __shared__ uint32_t xb[2][NW];  // lane 63: top mask bits of this step's half-steps
+    const uint32_t xip = (uint32_t)a.all_p, xiq = (uint32_t)a.all_q;
+
+    // [slot][array][half]; arrays 0 = x-(even), 1 = x-(odd), 2 = y-(even), 3 = y-(odd)
+    uint32_t Wn[NS][4][2];
+    uint32_t nb = 0;  // lane 63: the next wave's next-word bits, half-step h in bit 32-2K+h
+    int buf = 0;
+
+    auto load_row = [&](uint32_t (&row)[4][2], int r) {
+        const int32_t rb = (int32_t)((r & ymask) * WR * 8);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const auto v = __builtin_amdgcn_raw_buffer_load_b64(rsrc[c], (int)voff, rb, 0);
+            row[c][0] = v[0];
+            row[c][1] = v[1];
+        }
+    };
+    const int s0 = y0 - 2 * H + 1;
+
+    // Step s = s0 + k holds row s+j in slot (u+j) mod NS, u = k mod NS; rows
+    // s .. s+2K are the window and rows up to s+2K+DIST-1 are in flight.  s0
+    // is odd and NS even, so step u is shifted iff u is odd.  KC is k for the
+    // first 2NS steps (the halo rows above y0-2K+h that half-step h skips,
+    // k < 2h, the origin row of band 0 at k = 2K .. 4K-1 and the rows above
+    // y0, k < 4K-1, which are not stored, all fall there) and -1 after.
+    auto step = [&](auto U, auto KC, int s) __attribute__((always_inline)) {
+        constexpr int u = decltype(U)::value % NS;
+        constexpr int kc = decltype(KC)::value;
+        constexpr bool SH = (u & 1) != 0;
+        if (s >= y1) return false;
+        auto sl = [](int j) { return (u + j) % NS; };
+        // Every step loads a row, so that the wait before a row's first use
+        // counts the same memory operations on every path; the last steps
+        // load the band's last row again in place of rows it does not need.
+        load_row(Wn[sl(H + DIST)], min(s + H + DIST, y1 + H - 1));
+        uint32_t msb = 0;
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            const int j = H - 1 - h;
+            const int par = h & 1;
+            if (kc >= 0 && kc < 2 * h) {  // row above y0-2K+h: feeds none of the band's rows
+                if (SH) msb <<= 1;
+                continue;
+            }
+            uint32_t mp_lo, mq_lo;
+            fixed_halfstep<SH, HASQ>(Wn[sl(j)][par], Wn[sl(j)][2 + par], Wn[sl(j + 1)][3 - par], Wn[sl(j)][1 - par],
+                                     nb >> (32 - H + h), xip, xiq, msb, mp_lo, mq_lo);
+            // row 0 of band 0 is row s0+k+j with s0 = 1-4K
+            if (kc >= 0 && par == 0 && kc + j == 2 * H - 1) {
+                if (y0 == 0 && voff == 0) {
+                    const int64_t dh = 2 * (int64_t)(mp_lo & 1u) - 2 * (int64_t)(mq_lo & 1u);
+                    if (dh != 0) *a.h0 += dh;
+                }
+            }
+        }
+        // exchange, one barrier: an aligned step passes on the next step's
+        // next-word bits (bit 0 of the x+ words of its half-steps, collected
+        // from the right), a shifted step its top mask bits
+        uint32_t v = 0;
+        if constexpr (!SH) {
+#pragma unroll
+            for (int h = 0; h < H; ++h) v = __builtin_amdgcn_alignbit(Wn[sl(H - h)][1 - (h & 1)][0], v, 1u);
+        }
+        uint32_t pm, nv;
+        if constexpr (NW > 1) {
+            if (lane == 0) xa[buf][wv] = v;
+            if (lane == 63) xb[buf][wv] = msb;
+            __syncthreads();
+            pm = xb[buf][(wv + NW - 1) % NW];
+            nv = xa[buf][(wv + 1) % NW];
+            buf ^= 1;
+        } else {
+            pm = (uint32_t)__builtin_amdgcn_readlane((int)msb, 63);
+            nv = (uint32_t)__builtin_amdgcn_readlane((int)v, 0);
+        }
+        if constexpr (SH) {
+            // lane 0's carries: bit 0 of the x+ word of each half-step's row
+            const uint32_t pms = (uint32_t)__builtin_amdgcn_readfirstlane((int)pm);
+            if (lane == 0) {
+#pragma unroll
+                for (int h = 0; h < H; ++h) Wn[sl(H - 1 - h)][1 - (h & 1)][0] ^= (pms >> (H - 1 - h)) & 1u;
+            }
+        } else {
+            nb = nv;
+        }
+        if (kc < 0 || kc >= 2 * H - 1) {  // row s >= y0
+            const int32_t rb = (int32_t)((s & ymask) * WR * 8);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                __attribute__((ext_vector_type(2))) uint32_t w;
+                w[0] = Wn[sl(0)][c][0];
+                w[1] = Wn[sl(0)][c][1];
+                __builtin_amdgcn_raw_buffer_store_b64(w, rdst[c], (int)voff, rb, 0);
+            }
+        }
+        return true;
+    };
+
+    // prologue: the window and the rows in flight before step s0; rows above
+    // y0-2K are not needed and start as zero
+#pragma unroll
+    for (int j = 0; j < H + DIST; ++j) {
+        if (j >= H - 1) {  // s0 + j >= y0 - 2K
+            load_row(Wn[j], s0 + j);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) Wn[j][c][0] = Wn[j][c][1] = 0u;
+        }
+    }
+    auto first = [&](auto KC, int s) __attribute__((always_inline)) { return step(KC, KC, s); };
+    auto plain = [&](auto U, int s) __attribute__((always_inline)) {
+        return step(U, std::integral_constant<int, -1>{}, s);
+    };
+    // the first step past the band ends the sweep
+    if (unrolled_steps_while(first, s0, std::make_integer_sequence<int, 2 * NS>{}))
+        for (int s = s0 + 2 * NS; unrolled_steps_while(plain, s, std::make_integer_sequence<int, NS>{}); s += NS) {
+        }
+}
+
 template <int NW, int I, int K>
 hipError_t launch_block(const SweepArgs& a, XiMode mode, bool has_q, const uint64_t* src, uint64_t* dst,
                         int32_t band, hipStream_t stream)
@@ -478,7 +703,13 @@ hipError_t launch_block(const SweepArgs& a, XiMode mode, bool has_q, const uint6
     const dim3 grid((unsigned)(a.Y / band));
     const dim3 block(NW * 64);
     if (mode == XiMode::Mask && a.ndraw == 0) {
-        if constexpr (I == 1 && K >= kLdsDepth) {
+        if constexpr (I == 1 && K >= kFixedDeepDepth) {
+            // the p = 1 form needs every p-draw accepted; p = 0 goes through the general masks
+            if (has_q || a.all_p == 0)
+                hipLaunchKernelGGL((mcs_fixed_kernel<NW, K, 3, true>), grid, block, 0, stream, a, src, dst, band);
+            else
+                hipLaunchKernelGGL((mcs_fixed_kernel<NW, K, 3, false>), grid, block, 0, stream, a, src, dst, band);
+        } else if constexpr (I == 1 && K >= kLdsDepth) {
             if (has_q) hipLaunchKernelGGL((mcs_block_lds_kernel<NW, K, true>), grid, block, 0, stream, a, src, dst, band);
             else hipLaunchKernelGGL((mcs_block_lds_kernel<NW, K, false>), grid, block, 0, stream, a, src, dst, band);
         } else {
@@ -531,8 +762,10 @@ hipError_t launch_depth(const SweepArgs& a, XiMode mode, bool has_q, const uint6
 
 }  // namespace
 
-// Passes of 5..8 MCS (draw-free only), built in their own translation unit.
+// Passes of 5..12 MCS (draw-free only), built in translation units of their own.
 hipError_t launch_mcs_fused_deep(const SweepArgs& a, XiMode mode, bool has_q, const uint64_t* src, uint64_t* dst,
                                  int32_t band, int32_t depth, hipStream_t stream);
+hipError_t launch_mcs_fused_deeper(const SweepArgs& a, bool has_q, const uint64_t* src, uint64_t* dst, int32_t band,
+                                   int32_t depth, hipStream_t stream);
 
 }  // namespace sca

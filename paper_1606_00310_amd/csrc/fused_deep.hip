@@ -1,6 +1,7 @@
 // fused_deep.hip -- the temporally blocked passes of 5..8 MCS (draw-free
-// probabilities only; kernel in fused.hpp), in a translation unit of their own
-// so that they compile in parallel with the shallower ones.
+// probabilities only; kernels in fused.hpp), in a translation unit of their
+// own so that they compile in parallel with the shallower ones; 9..12 MCS are
+// passed on to fused_deeper.hip.
 #include "fused.hpp"
 
 namespace sca {
@@ -13,6 +14,12 @@ hipError_t launch_mcs_fused_deep(const SweepArgs& a, XiMode mode, bool has_q, co
     case 6: return launch_depth<6>(a, mode, has_q, src, dst, band, stream);
     case 7: return launch_depth<7>(a, mode, has_q, src, dst, band, stream);
     case 8: return launch_depth<8>(a, mode, has_q, src, dst, band, stream);
+    case 9:
+    case 10:
+    case 11:
+    case 12:
+        if (mode != XiMode::Mask || a.ndraw != 0) return hipErrorInvalidValue;
+        return launch_mcs_fused_deeper(a, has_q, src, dst, band, depth, stream);
     default: return hipErrorInvalidValue;
     }
 }

@@ -116,8 +116,8 @@ def test_headline_half_windows(orc, sca):
 
 
 def test_headline_p1_odd_length_windows(orc, sca):
-    """p = 1 for 21 MCS (two 8-MCS passes of the LDS-window kernel and a
-    5-MCS remainder as passes of 3 and 2) must give the closed form; then
+    """p = 1 for 21 MCS (with 12-MCS passes, no whole pair of them: the
+    remainder runs as passes of 11 and 10 MCS) must give the closed form; then
     p = 1, q = 1/2 for 3 more MCS, whose windows the oracle computes from the
     closed-form state at t = 21 (flat slopes, heights raised by 42)."""
     from paper_1606_00310_amd.inputs import HEADLINE as w

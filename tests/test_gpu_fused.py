@@ -50,8 +50,8 @@ def test_fused_vs_oracle(orc, sca, X, Y, p, q, persite, depth):
 DRAW_FREE = [(1.0, 0.0), (0.0, 1.0), (1.0, 1.0)]
 
 
-@pytest.mark.parametrize("X,Y", [(8192, 32), (16384, 64), (65536, 32), (131072, 32)])
-@pytest.mark.parametrize("p,q", DRAW_FREE)
+@pytest.mark.parametrize("X,Y", [(8192, 32), (16384, 64), (32768, 32), (65536, 32), (131072, 32)])
+@pytest.mark.parametrize("p,q", DRAW_FREE + [(0.0, 0.0)])
 @pytest.mark.parametrize("depth", [5, 6, 7, 8])
 def test_deep_fused_vs_oracle(orc, sca, X, Y, p, q, depth):
     """Passes deeper than 4 MCS (draw-free p, q; lowered to 5 at X = 2^17)."""
@@ -60,6 +60,26 @@ def test_deep_fused_vs_oracle(orc, sca, X, Y, p, q, depth):
     n = 2 * depth + 3
     lat = sca.Lattice(X, Y, seed=seed)
     lat.set_blocking(depth, 16)
+    lat.step(n, p, q)
+    st = orc.flat(X, Y, track_heights=False)
+    orc.run(st, n, p, q, seed=seed)
+    torch.cuda.synchronize()
+    assert np.array_equal(lat.slopes.cpu().numpy().view(np.uint64), orc.pack(st))
+    assert lat.meta() == (st.t, st.h0)
+
+
+@pytest.mark.parametrize("p,q", DRAW_FREE + [(0.0, 0.0)])
+@pytest.mark.parametrize("depth,band,Y", [(9, 32, 64), (10, 32, 64), (11, 32, 64), (12, 32, 64), (12, 64, 128),
+                                          (12, 256, 512)])
+def test_deeper_fused_vs_oracle(orc, sca, p, q, depth, band, Y):
+    """Passes of 9..12 MCS, which only X = 2^16 runs (one word per lane of a
+    512-thread workgroup); two whole passes and a 3-MCS remainder."""
+    X = 65536
+    _say(f"[deeper] Y={Y} p={p} q={q} depth={depth} band={band}")
+    seed = 91 + depth + Y
+    n = 2 * depth + 3
+    lat = sca.Lattice(X, Y, seed=seed)
+    lat.set_blocking(depth, band)
     lat.step(n, p, q)
     st = orc.flat(X, Y, track_heights=False)
     orc.run(st, n, p, q, seed=seed)
@@ -112,6 +132,6 @@ def test_fused_graph_and_disable(sca):
     torch.cuda.synchronize()
     assert torch.equal(a.slopes, b.slopes) and torch.equal(b.slopes, c.slopes)
     assert a.meta() == b.meta() == c.meta()
-    for bad in [(1, 12), (9, 16), (-2, 0)]:
+    for bad in [(1, 12), (13, 32), (-2, 0)]:
         with pytest.raises(sca.ScaError):
             a.set_blocking(*bad)
