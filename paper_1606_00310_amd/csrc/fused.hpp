@@ -313,7 +313,8 @@ __global__ __launch_bounds__(NW * 64) void mcs_block_kernel(SweepArgs a, const u
     }
 }
 
-// Draw-free passes of K >= kLdsDepth MCS for rows of one word per lane.  The
+// Draw-free passes of K = kLdsDepth MCS for rows of one word per lane (and
+// at X = 2^17 with 1024-thread workgroups).  The
 // 2K+2-row register window of mcs_block_kernel no longer fits the 128 VGPRs
 // that two 512-thread workgroups per CU allow, so the two newest rows stay in
 // LDS: row s+2K, of which half-step 0 needs only the odd-sublattice y-slopes
@@ -324,13 +325,12 @@ __global__ __launch_bounds__(NW * 64) void mcs_block_kernel(SweepArgs a, const u
 // before the previous step's barrier.
 constexpr int kLdsDepth = 6;
 // From this depth on, draw-free passes of one word per lane run one
-// workgroup per CU anyway, and the register window with loads three steps
-// ahead (mcs_fixed_kernel) replaces the LDS window.
+// workgroup per CU anyway, and the register window with rows loaded ahead
+// (mcs_fixed_kernel) replaces the LDS window.
 constexpr int kFixedDeepDepth = 7;
 
 // Two 512-thread workgroups per CU need at most 128 VGPRs: the 6-MCS kernel
-// fits (121); the 7- and 8-MCS kernels need more and run one workgroup per
-// CU, which suits 256-row bands on a 65536-row lattice.
+// fits (121), and so does its 1024-thread form at X = 2^17.
 template <int NW, int K, bool HASQ>
 __global__ __launch_bounds__(NW * 64) void mcs_block_lds_kernel(SweepArgs a, const uint64_t* src, uint64_t* dst,
                                                                 int32_t band)
