@@ -111,6 +111,11 @@ __device__ __forceinline__ void blocked_passes(SweepArgs a, uint64_t* S, uint64_
     const int lane = threadIdx.x & 63, gbase = lane & ~(G - 1);
     const int nxl = gbase | ((gl + 1) & (G - 1)), pvl = gbase | ((gl - 1) & (G - 1));
     const bool active = g < nbands;
+    // Waves whose groups are all beyond the last band only take part in the
+    // barriers.  The test is made a scalar value (readfirstlane), so that the
+    // branch on it is a uniform jump and each wave meets exactly one of the
+    // two barrier sequences.
+    const bool wave_idle = __builtin_amdgcn_readfirstlane((int)(threadIdx.x & ~63u) / G >= nbands ? 1 : 0) != 0;
     const int bh = a.Y / nbands;
     const int y0 = g * bh;
     const int ymask = a.Y - 1;
@@ -141,9 +146,15 @@ __device__ __forceinline__ void blocked_passes(SweepArgs a, uint64_t* S, uint64_
     for (int pass = 0; pass < npass; ++pass) {
         a.t = t0 + (uint32_t)(pass * K);
         if (active) {
+            uint64_t keep[H][4];  // all loads first, then all stores
+#pragma unroll
             for (int j = 0; j < H; ++j)
 #pragma unroll
-                for (int c = 0; c < 4; ++c) st(rsv, svoff(g, j, c), ld(rs[c], soff(y0 + j)));
+                for (int c = 0; c < 4; ++c) keep[j][c] = ld(rs[c], soff(y0 + j));
+#pragma unroll
+            for (int j = 0; j < H; ++j)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) st(rsv, svoff(g, j, c), keep[j][c]);
         }
         __syncthreads();
         uint64_t Wn[NS][4][1];
@@ -152,11 +163,8 @@ __device__ __forceinline__ void blocked_passes(SweepArgs a, uint64_t* S, uint64_
         // load keeps one buffer descriptor.  Rows below y0-2K feed no
         // half-step the band needs; rows from y1 on come from the next band's
         // save area.
-        auto load_row = [&](uint64_t (&row)[4][1], int rel) {
-            if (rel < -H) {
-#pragma unroll
-                for (int c = 0; c < 4; ++c) row[c][0] = 0ull;
-            } else if (rel >= bh) {
+        auto load_step_row = [&](uint64_t (&row)[4][1], int rel) {  // rel >= -2K
+            if (rel >= bh) {
 #pragma unroll
                 for (int c = 0; c < 4; ++c) row[c][0] = ld(rsv, svoff(nxt, rel - bh, c));
             } else {
@@ -165,11 +173,20 @@ __device__ __forceinline__ void blocked_passes(SweepArgs a, uint64_t* S, uint64_
                 for (int c = 0; c < 4; ++c) row[c][0] = ld(rs[c], soff(rr));
             }
         };
-        if (active) {
+        auto load_row = [&](uint64_t (&row)[4][1], int rel) {
+            if (rel < -H) {
 #pragma unroll
-            for (int j = 0; j < R; ++j) load_row(Wn[j], j - 2 * H + 1);
-        }
+                for (int c = 0; c < 4; ++c) row[c][0] = 0ull;
+            } else {
+                load_step_row(row, rel);
+            }
+        };
         const int nsteps = bh + 2 * H - 1;  // the same for every group: uniform barriers
+        // Stores of groups beyond the last band (in a wave that also holds
+        // active groups) go to an offset outside the arrays, which the buffer
+        // unit drops; their loads read valid rows, so the sweep needs no
+        // per-group branch.
+        const int drop = active ? 0 : 0x7ffffff8;
         // Step k holds relative row q+j (q = k-2H+1) in slot (u+j) mod NS,
         // u = k mod NS: the sweep is unrolled NS steps deep so that the window
         // rotates through the slots instead of being moved, and a step's rows
@@ -179,11 +196,13 @@ __device__ __forceinline__ void blocked_passes(SweepArgs a, uint64_t* S, uint64_
             constexpr int u = decltype(U)::value;
             if (k >= nsteps) return;
             if (k == 2 * H) __syncthreads();  // every band is done with its upper halo
-            if (!active) return;
             auto sl = [](int j) { return (u + j) % NS; };
             constexpr bool shifted = (u & 1) != 0;
             const int q = k - 2 * H + 1;      // this step's first window row, relative to y0
-            if (q + 1 < bh) load_row(Wn[sl(H + 1)], q + 1 + H);
+            // every step loads a row (the last one reloads the last saved row,
+            // unused), so that the wait before a row's first use counts the
+            // same memory operations on every path
+            load_step_row(Wn[sl(H + 1)], min(q + 1 + H, bh + H - 1));
 #pragma unroll
             for (int h = 0; h < H; ++h) {
                 const int j = H - 1 - h;
@@ -213,17 +232,23 @@ __device__ __forceinline__ void blocked_passes(SweepArgs a, uint64_t* S, uint64_
                 } else {
                     D[0] ^= M[0];
                 }
-                if (par == 0 && rel == 0 && g == 0 && gl == 0) {  // site (0,0)
+                if (par == 0 && rel == 0 && g == 0 && gl == 0) {  // site (0,0); an atomic needs no wait
                     const int64_t dh = 2 * (int64_t)(mp0 & 1ull) - 2 * (int64_t)(mq0 & 1ull);
-                    if (dh != 0) *a.h0 += dh;
+                    if (dh != 0) atomicAdd((unsigned long long*)a.h0, (unsigned long long)dh);
                 }
             }
             if (q >= 0) {
 #pragma unroll
-                for (int c = 0; c < 4; ++c) st(rs[c], soff(y0 + q), Wn[sl(0)][c][0]);
+                for (int c = 0; c < 4; ++c) st(rs[c], soff(y0 + q) | drop, Wn[sl(0)][c][0]);
             }
         };
-        for (int k = 0; k < nsteps; k += NS) unrolled_steps(step, k, std::make_integer_sequence<int, NS>{});
+        if (!wave_idle) {
+#pragma unroll
+            for (int j = 0; j < R; ++j) load_row(Wn[j], j - 2 * H + 1);
+            for (int k = 0; k < nsteps; k += NS) unrolled_steps(step, k, std::make_integer_sequence<int, NS>{});
+        } else {
+            __syncthreads();  // the one at row step 2K (nsteps > 2K)
+        }
         __syncthreads();
     }
 }

@@ -155,18 +155,20 @@ __global__ __launch_bounds__(NW * 64) void mcs_block_kernel(SweepArgs a, const u
     uint32_t nb0 = 0;  // lane 63: bit 0 of the next wave's first word, per (half-step, slot)
     int buf = 0;
 
+    auto load = [&](uint64_t (&row)[4][I], int r) {
+        const int32_t rb = (int32_t)((r & ymask) * W * 8);
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int i = 0; i < I; ++i) {
+                const auto v = __builtin_amdgcn_raw_buffer_load_b64(rsrc[c], (int)off(i), rb, 0);
+                row[c][i] = (uint64_t)v[0] | ((uint64_t)v[1] << 32);
+            }
+    };
     // rows below y0-2K feed no half-step the band needs: not loaded
     auto load_row = [&](uint64_t (&row)[4][I], int r) {
-        const int rr = r & ymask;
         if (r >= y0 - H) {
-            const int32_t rb = (int32_t)(rr * W * 8);
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-#pragma unroll
-                for (int i = 0; i < I; ++i) {
-                    const auto v = __builtin_amdgcn_raw_buffer_load_b64(rsrc[c], (int)off(i), rb, 0);
-                    row[c][i] = (uint64_t)v[0] | ((uint64_t)v[1] << 32);
-                }
+            load(row, r);
         } else {
 #pragma unroll
             for (int c = 0; c < 4; ++c)
@@ -212,7 +214,10 @@ __global__ __launch_bounds__(NW * 64) void mcs_block_kernel(SweepArgs a, const u
         constexpr int u = decltype(U)::value;
         if (s >= y1) return;
         auto sl = [](int j) { return (u + j) % NS; };
-        if (s + 1 < y1) load_row(Wn[sl(H + 1)], s + 1 + H);
+        // Every step loads a row (the last one reloads the band's last row in
+        // place of one it does not need), so that the wait before a row's
+        // first use counts the same memory operations on every path.
+        load(Wn[sl(H + 1)], min(s + 1 + H, y1 + H - 1));
         const bool shifted = ROT ? (u & 1) != 0 : (s & 1) == 0;
         uint32_t msb_all = 0;
 #pragma unroll
@@ -237,8 +242,9 @@ __global__ __launch_bounds__(NW * 64) void mcs_block_kernel(SweepArgs a, const u
                                                                Wn[sl(j + 1)][2 + (1 - par)], Wn[sl(j)][1 - par],
                                                                nbits, msb_all, h * I, mp0, mq0);
             if (par == 0 && rr == 0 && r >= y0 && r < y1 && wo == 0) {
+                // one lane of the grid; an atomic needs no wait for the old value
                 const int64_t dh = 2 * (int64_t)(mp0 & 1ull) - 2 * (int64_t)(mq0 & 1ull);
-                if (dh != 0) *a.h0 += dh;
+                if (dh != 0) atomicAdd((unsigned long long*)a.h0, (unsigned long long)dh);
             }
         }
         // exchange: this step's top mask bits (for the first lanes' carries,

@@ -248,10 +248,11 @@ __device__ __forceinline__ void halfstep_rows(const SweepArgs& a, uint64_t* S, i
             syQ[w] = C[i];
             sxQ[w] = D[i];
         }
-        // Site (0,0) is bit 0 of word 0 of row 0 in the even sublattice.
+        // Site (0,0) is bit 0 of word 0 of row 0 in the even sublattice (one
+        // lane; an atomic add needs no wait for the old value).
         if (par == 0 && y == 0 && gl == 0) {
             const int64_t dh = 2 * (int64_t)(mp0 & 1ull) - 2 * (int64_t)(mq0 & 1ull);
-            if (dh != 0) *a.h0 += dh;
+            if (dh != 0) atomicAdd((unsigned long long*)a.h0, (unsigned long long)dh);
         }
     }
 }
