@@ -438,7 +438,7 @@ __global__ __launch_bounds__(NW * 64) void mcs_block_lds_kernel(SweepArgs a, con
             }
             if (par == 0 && rr == 0 && r >= y0 && r < y1 && wo == 0) {
                 const int64_t dh = 2 * (int64_t)(mp0 & 1ull) - 2 * (int64_t)(mq0 & 1ull);
-                if (dh != 0) *a.h0 += dh;
+                if (dh != 0) atomicAdd((unsigned long long*)a.h0, (unsigned long long)dh);
             }
         }
         {
@@ -634,7 +634,7 @@ __global__ __launch_bounds__(NW * 64) void mcs_fixed_kernel(SweepArgs a, const u
             if (kc >= 0 && par == 0 && kc + j == 2 * H - 1) {
                 if (y0 == 0 && voff == 0) {
                     const int64_t dh = 2 * (int64_t)(mp_lo & 1u) - 2 * (int64_t)(mq_lo & 1u);
-                    if (dh != 0) *a.h0 += dh;
+                    if (dh != 0) atomicAdd((unsigned long long*)a.h0, (unsigned long long)dh);
                 }
             }
         }
