@@ -4,7 +4,7 @@ A step is one Monte-Carlo step (the even and the odd half-step) over the
 2^16 x 2^16 lattice (1 GiB of packed slopes, resident in HBM), p = 1, q = 0,
 seed 42, grown from the flat surface.  The metric is site updates per second
 (X * Y * steps / time), timed with HIP events on the stream the kernels run
-on.  The sweep runs as temporally blocked passes of 12 MCS; the roofline
+on.  The sweep runs as temporally blocked passes of 13 MCS; the roofline
 object prices that pass kernel against HBM bandwidth with its algorithmic
 traffic: every packed slope word is read once and written once per pass,
 X*Y/4 bytes each way (the paper's bandwidth model in Sec. III charges 1 byte
@@ -294,11 +294,11 @@ def main():
     w = HEADLINE
     K, Wm = args.steps, args.warmup
     # The sweep runs as temporally blocked passes of DEPTH MCS each (all
-    # 24 half-steps of twelve MCS in one sweep over the state, BAND-row
+    # 26 half-steps of thirteen MCS in one sweep over the state, BAND-row
     # bands per workgroup), an even number of passes per call; the MCS left
     # over run as two shallower passes.  Every pass reads the packed state once
     # and writes it once: X*Y/4 bytes each way.
-    DEPTH, BAND = 12, 256
+    DEPTH, BAND = 13, 256
     n_pass = (K // DEPTH) & ~1
     n_fused = n_pass * DEPTH
     torch.cuda.synchronize()

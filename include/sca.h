@@ -136,15 +136,15 @@ int sca_autocorr(sca_ctx* ctx, const void* snap_dev, int64_t out4[4], double* c_
 /* Current MCS count t and origin height h(0,0).  Synchronizes. */
 int sca_get_meta(sca_ctx* ctx, int64_t* t, int64_t* h0);
 
-/* Temporal blocking of sca_step: depth = MCS per fused pass (1..12), 0 =
+/* Temporal blocking of sca_step: depth = MCS per fused pass (1..13), 0 =
  * never fuse, -1 = automatic; band = rows per workgroup (a power of two >= 4
  * and >= 2*depth that divides Y, with Y >= 2*band), 0 = automatic (the
  * tallest of 256 (p, q in {0, 1}) or 128, then 64, 32, 16, 8, that leaves
  * enough workgroups to fill the chip).
- * Passes run at most 12 MCS deep when p and q are both 0 or 1 (no random
+ * Passes run at most 13 MCS deep when p and q are both 0 or 1 (no random
  * words) and X = 2^16, at most 8 deep for smaller X and 6 for X = 2^17, and
  * at most 4 deep with random words: a larger depth is lowered to that limit
- * when sca_step runs.  The automatic depth without random words is 12 on
+ * when sca_step runs.  The automatic depth without random words is 13 on
  * bands of >= 256 rows and 10 on 128-row bands (both lowered to the limit
  * above), 5 on 64-row bands; with random words 4 on bands of >= 128 rows and
  * 3 on 32- and 64-row bands; 2 on 16-row bands and 1 on smaller ones; the

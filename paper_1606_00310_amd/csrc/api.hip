@@ -261,7 +261,7 @@ int sca_step_ex(sca_ctx* c, int64_t n_mcs, double p, double q, unsigned flags)
     // per-site path is ALU-bound and runs unfused.
     const int64_t nw = c->W >= 512 ? 8 : (c->W >= 64 ? c->W / 64 : 1);
     // Without random words (p, q in {0, 1}) a pass costs little more than
-    // a shallower one as long as its window fits the registers: 12 MCS at
+    // a shallower one as long as its window fits the registers: 13 MCS at
     // X = 2^16 and 8 below (the register-window kernels), 6 at X = 2^17 (the
     // LDS-window kernel with 1024-thread workgroups), on bands of up to 256
     // rows (about one workgroup per CU); passes with draws are ALU-bound and
@@ -277,7 +277,7 @@ int sca_step_ex(sca_ctx* c, int64_t n_mcs, double p, double q, unsigned flags)
     int32_t depth = c->depth;
     if (depth < 0) {
         depth = persite ? 0
-                        : band >= 256 ? (draw_free ? 12 : 4)
+                        : band >= 256 ? (draw_free ? 13 : 4)
                         : band >= 128 ? (draw_free ? 10 : 4)
                         : band >= 64 ? (draw_free ? 5 : 3)
                         : band >= 32 ? 3
@@ -446,7 +446,7 @@ int sca_get_meta(sca_ctx* c, int64_t* t, int64_t* h0)
 
 int sca_set_blocking(sca_ctx* c, int32_t depth, int32_t band)
 {
-    if (!c || depth < -1 || depth > 12 || band < 0 || (band > 0 && (band < 4 || (band & (band - 1)) != 0)))
+    if (!c || depth < -1 || depth > 13 || band < 0 || (band > 0 && (band < 4 || (band & (band - 1)) != 0)))
         return SCA_EINVAL;
     c->depth = depth;
     c->band = band;

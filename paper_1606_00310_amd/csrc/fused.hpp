@@ -40,8 +40,8 @@ constexpr int kMaxDepthMask = 4;
 constexpr int kMaxDepthPerSite = 4;
 constexpr int kMaxDepthFixed = 8;
 // X = 2^16 (512 words per row): the register window of mcs_fixed_kernel holds
-// up to 12 MCS in one workgroup per CU.
-constexpr int kMaxDepthFixed512 = 12;
+// up to 13 MCS in one workgroup per CU.
+constexpr int kMaxDepthFixed512 = 13;
 constexpr int kMaxDepthWide = 5;  // two words per lane (X = 2^17)
 // LDS of one 1024-thread workgroup of the LDS-window kernel at X = 2^17
 constexpr int kWideLdsBytes = 3 * 4 * 1024 * 8 + 4 * 16 * 4;
@@ -543,18 +543,21 @@ __device__ __forceinline__ void fixed_halfstep(uint32_t (&A)[2], uint32_t (&B)[2
         D[0] ^= __builtin_amdgcn_alignbit(M[0], ph, 31u);
         D[1] ^= __builtin_amdgcn_alignbit(M[1], M[0], 31u);
         msb = __builtin_amdgcn_alignbit(msb, M[1], 31u);  // (msb << 1) | top bit
+        asm volatile("" : "+v"(msb));
     }
-    // Pin the new slopes here: left alone, the compiler sinks each update to
-    // the next step, where the words are read again, and keeps the masks of
-    // all 2K half-steps live until then (about 50 more VGPRs at K = 8).
+    // Pin the new slopes (and the top mask bits) here: left alone, the
+    // compiler sinks each update to where the words are read next, the next
+    // step, and keeps the masks of all 2K half-steps live until then (about
+    // 50 more VGPRs at K = 8).
     asm volatile("" : "+v"(A[0]), "+v"(A[1]), "+v"(B[0]), "+v"(B[1]), "+v"(C[0]), "+v"(C[1]), "+v"(D[0]), "+v"(D[1]));
 }
 
 // Deep draw-free passes for rows of one word per lane (X = 2^13 .. 2^16)
 // with one workgroup per CU: the register window of 2K+1 rows plus DIST
 // rows in flight, loaded DIST steps ahead of use so that each load has
-// DIST row steps of compute to arrive in (3; at K = 12 the window alone
-// fills the registers and a step of 24 half-steps hides a load by itself).
+// DIST row steps of compute to arrive in (3; at K = 12 and 13 the window
+// alone fills the registers and a step of 2K half-steps hides a load by
+// itself).
 // Without LDS DMA the one barrier per step waits only for LDS, not for loads
 // or stores.  The first two unrolled rounds of the sweep, which hold the
 // band's upper halo, the origin row of band 0 and the rows not yet stored,
@@ -582,8 +585,10 @@ __global__ __launch_bounds__(NW * 64) void mcs_fixed_kernel(SweepArgs a, const u
         rsrc[c] = __builtin_amdgcn_make_buffer_rsrc((void*)(src + c * P), (short)0, plane_bytes, kBufferWord3);
         rdst[c] = __builtin_amdgcn_make_buffer_rsrc((void*)(dst + c * P), (short)0, plane_bytes, kBufferWord3);
     }
-    __shared__ uint32_t xa[2][NW];  // lane 0: bit 0 of the x+ words of the next step's half-steps
-    __shared__ uint32_t xb[2][NW];  // lane 63: top mask bits of this step's half-steps
+    // per wave and step: the next-word bits an aligned step passes to the
+    // wave before it, or the top mask bits a shifted step passes to the wave
+    // after it (double-buffered, one barrier per step)
+    __shared__ uint32_t xs[2][NW];
     const uint32_t xip = (uint32_t)a.all_p, xiq = (uint32_t)a.all_q;
 
     // [slot][array][half]; arrays 0 = x-(even), 1 = x-(odd), 2 = y-(even), 3 = y-(odd)
@@ -646,27 +651,24 @@ __global__ __launch_bounds__(NW * 64) void mcs_fixed_kernel(SweepArgs a, const u
 #pragma unroll
             for (int h = 0; h < H; ++h) v = __builtin_amdgcn_alignbit(Wn[sl(H - h)][1 - (h & 1)][0], v, 1u);
         }
-        uint32_t pm, nv;
+        const uint32_t out = SH ? (uint32_t)__builtin_amdgcn_readlane((int)msb, 63)
+                                : (uint32_t)__builtin_amdgcn_readlane((int)v, 0);
+        uint32_t in = out;  // one wave: the row wraps within it
         if constexpr (NW > 1) {
-            if (lane == 0) xa[buf][wv] = v;
-            if (lane == 63) xb[buf][wv] = msb;
+            if (lane == 0) xs[buf][wv] = out;
             __syncthreads();
-            pm = xb[buf][(wv + NW - 1) % NW];
-            nv = xa[buf][(wv + 1) % NW];
+            in = xs[buf][SH ? (wv + NW - 1) % NW : (wv + 1) % NW];
             buf ^= 1;
-        } else {
-            pm = (uint32_t)__builtin_amdgcn_readlane((int)msb, 63);
-            nv = (uint32_t)__builtin_amdgcn_readlane((int)v, 0);
         }
         if constexpr (SH) {
             // lane 0's carries: bit 0 of the x+ word of each half-step's row
-            const uint32_t pms = (uint32_t)__builtin_amdgcn_readfirstlane((int)pm);
+            const uint32_t pms = (uint32_t)__builtin_amdgcn_readfirstlane((int)in);
             if (lane == 0) {
 #pragma unroll
                 for (int h = 0; h < H; ++h) Wn[sl(H - 1 - h)][1 - (h & 1)][0] ^= (pms >> (H - 1 - h)) & 1u;
             }
         } else {
-            nb = nv;
+            nb = in;
         }
         if (kc < 0 || kc >= 2 * H - 1) {  // row s >= y0
             const int32_t rb = (int32_t)((s & ymask) * WR * 8);
@@ -768,7 +770,7 @@ hipError_t launch_depth(const SweepArgs& a, XiMode mode, bool has_q, const uint6
 
 }  // namespace
 
-// Passes of 5..12 MCS (draw-free only), built in translation units of their own.
+// Passes of 5..13 MCS (draw-free only), built in translation units of their own.
 hipError_t launch_mcs_fused_deep(const SweepArgs& a, XiMode mode, bool has_q, const uint64_t* src, uint64_t* dst,
                                  int32_t band, int32_t depth, hipStream_t stream);
 hipError_t launch_mcs_fused_deeper(const SweepArgs& a, bool has_q, const uint64_t* src, uint64_t* dst, int32_t band,

@@ -1,6 +1,6 @@
 // fused_deep.hip -- the temporally blocked passes of 5..8 MCS (draw-free
 // probabilities only; kernels in fused.hpp), in a translation unit of their
-// own so that they compile in parallel with the shallower ones; 9..12 MCS are
+// own so that they compile in parallel with the shallower ones; 9..13 MCS are
 // passed on to fused_deeper.hip.
 #include "fused.hpp"
 
@@ -18,6 +18,7 @@ hipError_t launch_mcs_fused_deep(const SweepArgs& a, XiMode mode, bool has_q, co
     case 10:
     case 11:
     case 12:
+    case 13:
         if (mode != XiMode::Mask || a.ndraw != 0) return hipErrorInvalidValue;
         return launch_mcs_fused_deeper(a, has_q, src, dst, band, depth, stream);
     default: return hipErrorInvalidValue;

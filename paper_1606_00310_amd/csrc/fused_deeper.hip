@@ -1,12 +1,13 @@
-// fused_deeper.hip -- draw-free passes of 9..12 MCS at X = 2^16 (512 words
+// fused_deeper.hip -- draw-free passes of 9..13 MCS at X = 2^16 (512 words
 // per row, one 512-thread workgroup per band; mcs_fixed_kernel in fused.hpp).
 #include "fused.hpp"
 
 namespace sca {
 namespace {
 
-// DIST: rows loaded ahead; 12-MCS passes keep one, which leaves their 26-row
-// window in 242 VGPRs without spills and runs as fast as three ahead.
+// DIST: rows loaded ahead; 12- and 13-MCS passes keep one, which leaves their
+// 26- and 28-row windows in 225 and 242 VGPRs without spills (with three
+// ahead the 12-MCS pass runs 3 % slower).
 template <int K, int DIST>
 hipError_t launch_fixed512(const SweepArgs& a, bool has_q, const uint64_t* src, uint64_t* dst, int32_t band,
                            hipStream_t stream)
@@ -31,6 +32,7 @@ hipError_t launch_mcs_fused_deeper(const SweepArgs& a, bool has_q, const uint64_
     case 10: return launch_fixed512<10, 3>(a, has_q, src, dst, band, stream);
     case 11: return launch_fixed512<11, 3>(a, has_q, src, dst, band, stream);
     case 12: return launch_fixed512<12, 1>(a, has_q, src, dst, band, stream);
+    case 13: return launch_fixed512<13, 1>(a, has_q, src, dst, band, stream);
     default: return hipErrorInvalidValue;
     }
 }

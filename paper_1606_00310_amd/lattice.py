@@ -96,7 +96,7 @@ class Lattice:
         return int(t.value)
 
     def set_blocking(self, depth: int = -1, band: int = 0):
-        """MCS per fused pass (1..12; 0 never fuses, -1 automatic) and rows per
+        """MCS per fused pass (1..13; 0 never fuses, -1 automatic) and rows per
         workgroup band (0 automatic)."""
         L.check(L.lib().sca_set_blocking(self._ctx, int(depth), int(band)), "sca_set_blocking")
 

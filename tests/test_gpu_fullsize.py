@@ -116,7 +116,7 @@ def test_headline_half_windows(orc, sca):
 
 
 def test_headline_p1_odd_length_windows(orc, sca):
-    """p = 1 for 21 MCS (with 12-MCS passes, no whole pair of them: the
+    """p = 1 for 21 MCS (with 13-MCS passes, no whole pair of them: the
     remainder runs as passes of 11 and 10 MCS) must give the closed form; then
     p = 1, q = 1/2 for 3 more MCS, whose windows the oracle computes from the
     closed-form state at t = 21 (flat slopes, heights raised by 42)."""

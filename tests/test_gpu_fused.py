@@ -70,9 +70,9 @@ def test_deep_fused_vs_oracle(orc, sca, X, Y, p, q, depth):
 
 @pytest.mark.parametrize("p,q", DRAW_FREE + [(0.0, 0.0)])
 @pytest.mark.parametrize("depth,band,Y", [(9, 32, 64), (10, 32, 64), (11, 32, 64), (12, 32, 64), (12, 64, 128),
-                                          (12, 256, 512)])
+                                          (13, 32, 64), (13, 256, 512)])
 def test_deeper_fused_vs_oracle(orc, sca, p, q, depth, band, Y):
-    """Passes of 9..12 MCS, which only X = 2^16 runs (one word per lane of a
+    """Passes of 9..13 MCS, which only X = 2^16 runs (one word per lane of a
     512-thread workgroup); two whole passes and a 3-MCS remainder."""
     X = 65536
     _say(f"[deeper] Y={Y} p={p} q={q} depth={depth} band={band}")
@@ -132,6 +132,6 @@ def test_fused_graph_and_disable(sca):
     torch.cuda.synchronize()
     assert torch.equal(a.slopes, b.slopes) and torch.equal(b.slopes, c.slopes)
     assert a.meta() == b.meta() == c.meta()
-    for bad in [(1, 12), (13, 32), (-2, 0)]:
+    for bad in [(1, 12), (14, 32), (-2, 0)]:
         with pytest.raises(sca.ScaError):
             a.set_blocking(*bad)

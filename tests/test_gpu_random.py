@@ -60,7 +60,7 @@ def test_random_small(orc, sca, lx, ly, p, q, seed, n, persite):
 @settings(max_examples=30, deadline=None, derandomize=True, database=None,
           suppress_health_check=[HealthCheck.too_slow, HealthCheck.function_scoped_fixture])
 @given(lx=st.integers(13, 17), ly=st.integers(4, 7), p=_prob(), q=_prob(), seed=st.integers(0, 2**64 - 1),
-       n=st.integers(0, 27), depth=st.integers(0, 12), lband=st.integers(2, 6))
+       n=st.integers(0, 27), depth=st.integers(0, 13), lband=st.integers(2, 6))
 def test_random_blocked(orc, sca, lx, ly, p, q, seed, n, depth, lband):
     band = 2**lband
     Y = 2**ly
