@@ -81,6 +81,30 @@ def _valu_per_update(tag):
     return c["valu_lane_instructions_per_site_update"]
 
 
+def pass_roofline(alg_bytes, avg_ms, counters):
+    """The pass kernel against HBM (algorithmic bytes per launch over the
+    launch time) and, when rocprofv3 counted its VALU instructions per launch
+    (`counters`, from _pass_counters), against the 32-bit VALU issue rate; the
+    roof the pass comes closer to is `bound`, the other one sits beside it.
+    `traffic` is the counted HBM bytes per launch, or None."""
+    achieved = alg_bytes / (avg_ms / 1e3) / 1e9
+    hbm = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4)}
+    roofline = dict(hbm)
+    valu = counters.get("valu", {}).get("sq_insts_valu_per_launch")
+    if valu:
+        # VALU lane instructions per launch (wave instructions x 64) over the launch time
+        va = valu * 64 / (avg_ms / 1e3)
+        alu = {"bound": "alu", "achieved": va, "peak": VALU_LANE_OPS, "unit": "VALU lane instructions/s",
+               "frac": round(va / VALU_LANE_OPS, 4)}
+        if alu["frac"] > hbm["frac"]:
+            roofline = dict(alu, hbm=hbm)
+        else:
+            roofline["alu"] = alu
+    roofline["traffic"] = counters.get("hbm_bytes_per_launch")
+    return roofline
+
+
 def time_path(torch, P, X, Y, p, q, seed, steps, warmup, force_persite=False, split=None, blocking=None):
     """Milliseconds for `steps` MCS after `warmup` MCS.  With split = m the
     timed region is recorded as two parts, the first m MCS (whole fused passes)
@@ -318,22 +342,9 @@ def main():
         avg_ms = ms / (2 * K)
         kernel = "halfstep_kernel<64,8,Mask,false>"
         per_update = alg_bytes / w.sites
-    achieved = alg_bytes / (avg_ms / 1e3) / 1e9
     pc = _pass_counters() if n_pass else {}
-    hbm = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": round(achieved / HBM_PEAK_GBS, 4)}
-    roofline = dict(hbm)
-    valu = pc.get("valu", {}).get("sq_insts_valu_per_launch")
-    if valu:
-        # VALU lane instructions per launch (wave instructions x 64) over the launch time
-        va = valu * 64 / (avg_ms / 1e3)
-        alu = {"bound": "alu", "achieved": va, "peak": VALU_LANE_OPS, "unit": "VALU lane instructions/s",
-               "frac": round(va / VALU_LANE_OPS, 4)}
-        if alu["frac"] > hbm["frac"]:
-            roofline = dict(alu, hbm=hbm)
-        else:
-            roofline["alu"] = alu
-    roofline.update({"traffic": pc.get("hbm_bytes_per_launch"), "kernel": kernel,
+    roofline = pass_roofline(alg_bytes, avg_ms, pc)
+    roofline.update({"kernel": kernel,
                      "alg_bytes_per_launch": alg_bytes, "mcs_per_launch": DEPTH if n_pass else 0.5,
                      "alg_bytes_per_site_update": per_update, "avg_launch_ms": round(avg_ms, 5),
                      "launches_timed": n_pass if n_pass else 2 * K})
