@@ -361,14 +361,25 @@ def main():
 
     if not args.no_paths:
         paths = {}
-        for wk, steps, ps in ((HEADLINE_HALF, 200, False), (HEADLINE_RANDOM, 200, False), (PERSITE, 100, False),
-                              (WIDE, 60, False)):
+        # X = 2^17 runs 6-MCS passes (the LDS-window kernel with 1024-thread
+        # workgroups) on 256-row bands, set explicitly so that its HBM roofline
+        # below knows the pass depth.
+        WIDE_DEPTH = 6
+        for wk, steps, ps, blk in ((HEADLINE_HALF, 200, False, None), (HEADLINE_RANDOM, 200, False, None),
+                                   (PERSITE, 100, False, None), (WIDE, 60, False, (WIDE_DEPTH, 256))):
             # 24 warm-up MCS: several whole passes over freshly allocated state
             # (the first passes over a new 8 GiB lattice pair run about 10 % slower)
-            pms = time_path(torch, P, wk.X, wk.Y, wk.p, wk.q, wk.seed, steps, 24, ps)
+            pms = time_path(torch, P, wk.X, wk.Y, wk.p, wk.q, wk.seed, steps, 24, ps, blocking=blk)
             rate = wk.sites * steps / (pms / 1e3)
             paths[wk.name] = {"value": rate, "unit": "site updates/s", "steps": steps,
                               "hbm_frac_1B_per_update": round(rate / (HBM_PEAK_GBS * 1e9), 4)}
+        # the 2^17 pass is bandwidth-bound: its algorithmic traffic is the state
+        # read and written once per pass, X*Y/4 bytes each way per WIDE_DEPTH MCS
+        pw = paths[WIDE.name]
+        wa = pw["value"] / (2 * WIDE_DEPTH) / 1e9  # passes/s x X*Y/2 bytes per pass
+        pw["roofline"] = {"bound": "hbm", "achieved": round(wa, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": round(wa / HBM_PEAK_GBS, 4), "mcs_per_pass": WIDE_DEPTH,
+                          "kernel": "mcs_block_lds_kernel<16,6,false>"}
         # The random-word paths are bound by the VALU (Philox4x32-10): priced
         # against 256 CUs x 64 lanes x 2.4 GHz of 32-bit VALU issue with the
         # VALU instructions per site update that rocprofv3's SQ_INSTS_VALU
