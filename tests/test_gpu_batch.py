@@ -39,6 +39,9 @@ def _reals():
         # rows of 16..64 words: temporally blocked passes when the configuration's depth is > 0
         R(2048, 512, 0.75, 0.25, 7, 16), R(4096, 256, 0.5, 0.0, 5, 17), R(8192, 128, 0.9375, 0.0625, 4, 18),
         R(2048, 64, 0.5, 0.0, 9, 19), R(8192, 32, 1.0, 0.0, 6, 20), R(2048, 1024, 0.93, 0.07, 3, 21),
+        # two bands only: the first wave holds active and idle row groups (the idle ones compute on valid
+        # rows and their stores are dropped), the other waves only take part in the barriers
+        R(2048, 32, 0.5, 0.0, 9, 22), R(1024, 32, 0.75, 0.25, 7, 23),
     ]
 
 
