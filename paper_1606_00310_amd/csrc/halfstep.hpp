@@ -33,6 +33,17 @@
 
 namespace sca {
 
+// One step of the and/or fold, acc <- b ? (R | acc) : (R & acc): the
+// majority of R, acc and the digit spread over the word (an all-ones or
+// all-zero scalar), one v_bitop3_b32 (truth table 0xE8) per 32-bit half.
+__device__ __forceinline__ uint64_t fold_digit(uint64_t r, uint64_t acc, uint32_t b)
+{
+    const uint32_t m = b ? ~0u : 0u;
+    const uint32_t lo = __builtin_amdgcn_bitop3_b32((uint32_t)r, (uint32_t)acc, m, 0xE8);
+    const uint32_t hi = __builtin_amdgcn_bitop3_b32((uint32_t)(r >> 32), (uint32_t)(acc >> 32), m, 0xE8);
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
 // Acceptance words for canonical word g, mask mode: the and/or fold of
 // n = ndraw draws, least significant binary digit first, generated from the
 // last Philox call backwards so that only one call's output is live.
@@ -46,12 +57,12 @@ __device__ __forceinline__ void mask_words(const SweepArgs& a, uint32_t g, bool 
         const uint64_t r1 = (uint64_t)o.v2 | ((uint64_t)o.v3 << 32);  // draw 2j+1
         const int d1 = 2 * j + 1;                                     // digit b_{2j+2}
         if (d1 < a.ndraw) {
-            ap = ((a.dig_p >> d1) & 1u) ? (r1 | ap) : (r1 & ap);
-            if (has_q) aq = ((a.dig_q >> d1) & 1u) ? (r1 | aq) : (r1 & aq);
+            ap = fold_digit(r1, ap, (a.dig_p >> d1) & 1u);
+            if (has_q) aq = fold_digit(r1, aq, (a.dig_q >> d1) & 1u);
         }
         const int d0 = 2 * j;                                         // digit b_{2j+1}
-        ap = ((a.dig_p >> d0) & 1u) ? (r0 | ap) : (r0 & ap);
-        if (has_q) aq = ((a.dig_q >> d0) & 1u) ? (r0 | aq) : (r0 & aq);
+        ap = fold_digit(r0, ap, (a.dig_p >> d0) & 1u);
+        if (has_q) aq = fold_digit(r0, aq, (a.dig_q >> d0) & 1u);
     }
     xp = ap | a.all_p;
     xq = has_q ? (aq | a.all_q) : 0;
