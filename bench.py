@@ -1,16 +1,19 @@
 """Throughput of the bit-vectorized octahedron-model SCA sweep on one MI355X.
 
-A step is one Monte-Carlo step (the even and the odd half-step) over the
-2^16 x 2^16 lattice (1 GiB of packed slopes, resident in HBM), p = 1, q = 0,
-seed 42, grown from the flat surface.  The metric is site updates per second
-(X * Y * steps / time), timed with HIP events on the stream the kernels run
-on.  The sweep runs as temporally blocked passes of 13 MCS; the roofline
-object prices that pass kernel against HBM bandwidth with its algorithmic
-traffic: every packed slope word is read once and written once per pass,
-X*Y/4 bytes each way (the paper's bandwidth model in Sec. III charges 1 byte
-per site update, one pass per half-step), and, beside it, against the 32-bit
-VALU issue rate with the instructions per pass that rocprofv3 counted; the
-roof the pass comes closer to is the bound.
+A step is one run of the sweep-throughput workload: the flat surface on the
+2^16 x 2^16 lattice (1 GiB of packed slopes, resident in HBM), 2000 MCS at
+p = 1, q = 0 (seed 42), then the exact height moments.  The metric is site
+updates per second (X * Y * 2000 * steps / time).  The sweep runs as the
+temporally blocked passes sca_plan_step reports (152 passes of 13 MCS and two
+of 12 for 2000 MCS); the warm-up steps run the same plan, so no kernel's first
+launch is timed.  The roofline object prices the whole-pass kernel, whose
+launches are timed with HIP events on the stream they run on: against HBM
+with its algorithmic traffic (every packed slope word read once and written
+once per pass, X*Y/4 bytes each way) and against the 32-bit VALU issue rate
+with the instructions per launch that rocprofv3 counted; the roof the pass
+comes closer to is the bound.  The paper's own bandwidth model (Sec. III: 1
+byte per site update, one pass per half-step) is reported under a key of its
+own.
 
 Prints one JSON line.
 """
@@ -135,24 +138,104 @@ def time_path(torch, P, X, Y, p, q, seed, steps, warmup, force_persite=False, sp
     return (ms, first) if split else ms
 
 
-def cpu_baseline(X, Y, p, q, seed, rows, budget_s, max_mcs=200):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_rate(X, Y, p, q, seed, rows, budget_s, threads=None, max_mcs=200):
     """The oracle, untuned, on a band of `rows` full-width rows of the same
     workload (a light-cone patch with a frozen border), one MCS at a time
-    until about budget_s seconds of CPU work."""
+    until about budget_s seconds of CPU work, with `threads` OpenMP threads
+    (default: all)."""
     import oracle
 
-    st = oracle.flat_patch(X, Y, 0, 0, X, rows, track_heights=False) if rows < Y else oracle.flat(X, Y, False)
-    n, dt = 0, 0.0
-    while dt < budget_s and n < max_mcs:
-        t0 = time.perf_counter()
-        oracle.run(st, 1, p, q, seed=seed)
-        dt += time.perf_counter() - t0
-        n += 1
-    sites = X * rows
-    return {"value": sites * n / dt, "unit": "site updates/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
+    prev = oracle.num_threads()
+    if threads:
+        oracle.set_num_threads(threads)
+    try:
+        used = oracle.num_threads()
+        st = oracle.flat_patch(X, Y, 0, 0, X, rows, track_heights=False) if rows < Y else oracle.flat(X, Y, False)
+        n, dt = 0, 0.0
+        while dt < budget_s and n < max_mcs:
+            t0 = time.perf_counter()
+            oracle.run(st, 1, p, q, seed=seed)
+            dt += time.perf_counter() - t0
+            n += 1
+    finally:
+        oracle.set_num_threads(prev)
+    return {"value": X * rows * n / dt, "unit": "site updates/s", "cores": used, "kind": "oracle",
             "sample": f"{X} x {rows} band of the {X}x{Y} p={p} q={q} workload (frozen border), {n} MCS "
-                      f"in {dt:.1f} s"}
+                      f"in {dt:.1f} s on {used} thread(s)"}
+
+
+def cpu_baseline(X, Y, p, q, seed, rows, budget_s):
+    """The oracle on all host cores (the reported value) and on one core."""
+    out = oracle_rate(X, Y, p, q, seed, rows, budget_s)
+    one = oracle_rate(X, Y, p, q, seed, max(16, rows // 16), budget_s / 2, threads=1)
+    out["one_core"] = {"value": one["value"], "cores": 1, "sample": one["sample"]}
+    out["cpu_model"] = cpu_model()
+    out["host_cpus"] = os.cpu_count()
+    return out
+
+
+def bench_headline(torch, P, w, steps, warmup):
+    """`steps` timed runs of workload w after `warmup` untimed ones.  A run
+    resets the lattice to the flat surface, advances w.n_mcs MCS and takes the
+    exact moments; its whole blocked passes are bracketed by HIP events on the
+    lattice's stream (the MCS after them, the remainder passes, run as a second
+    call, which gives bit-identical results)."""
+    lat = P.Lattice(w.X, w.Y, seed=w.seed)
+    plan = lat.plan(w.n_mcs, w.p, w.q)
+    n_main = plan["n_pass"] * plan["depth"]
+    rest = lat.plan(w.n_mcs - n_main, w.p, w.q) if w.n_mcs > n_main else None
+    stream = lat.stream
+
+    def run(evs=None):
+        lat.reset()
+        if evs:
+            evs[0].record(stream)
+        if n_main:
+            lat.step(n_main, w.p, w.q)
+        if evs:
+            evs[1].record(stream)
+        if rest:
+            lat.step(w.n_mcs - n_main, w.p, w.q)
+        return lat.roughness()
+
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    moments = []
+    start.record(stream)
+    for k in range(steps):
+        moments.append(run(evs[k]))
+    end.record(stream)
+    end.synchronize()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    pass_ms = sum(e0.elapsed_time(e1) for e0, e1 in evs)
+    t, h0 = lat.meta()
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    # p = 1, q = 0 from the flat surface: h = 2t + ((x+y)&1) after every MCS
+    closed = None
+    if (w.p, w.q) == (1.0, 0.0):
+        N, T = w.sites, w.n_mcs
+        closed = all(m[:3] == (N, N * (4 * T + 1) // 2, N * (8 * T * T + 4 * T + 1) // 2) for m in moments) \
+            and (t, h0) == (T, 2 * T)
+    return {"ms": ms, "pass_ms": pass_ms, "plan": plan, "rest_plan": rest, "n_main": n_main,
+            "closed_form_holds": closed}
 
 
 def bench_ensemble(torch, P, n=4096, solo_per_L=3, tune_scale=10, serving=True, solo=True):
@@ -270,16 +353,17 @@ def bench_ensemble(torch, P, n=4096, solo_per_L=3, tune_scale=10, serving=True, 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=26)
+    ap.add_argument("--steps", type=int, default=20, help="timed runs of the 2000-MCS workload")
+    ap.add_argument("--warmup", type=int, default=3, help="untimed runs before them")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--no-paths", action="store_true", help="skip the secondary paths")
     ap.add_argument("--cpu-rows", type=int, default=16384)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched ensemble and serving runs")
     ap.add_argument("--ensemble-only", action="store_true", help="only the batched ensemble (for profiling)")
     ap.add_argument("--only", choices=["random", "half", "persite", "wide"],
-                    help="time one secondary path for --steps MCS and print it (for profiling)")
+                    help="time one secondary path for --mcs MCS and print it (for profiling)")
+    ap.add_argument("--mcs", type=int, default=200, help="MCS timed by --only (after 24 warm-up MCS)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (torch copy_) three times, the known-size "
                          "reference for HBM byte counters")
@@ -306,9 +390,9 @@ def main():
 
     if args.only:
         wk = {"random": HEADLINE_RANDOM, "half": HEADLINE_HALF, "persite": PERSITE, "wide": WIDE}[args.only]
-        pms = time_path(torch, P, wk.X, wk.Y, wk.p, wk.q, wk.seed, args.steps, args.warmup)
-        print(json.dumps({"path": wk.name, "steps": args.steps, "ms": pms,
-                          "value": wk.sites * args.steps / (pms / 1e3)}), flush=True)
+        pms = time_path(torch, P, wk.X, wk.Y, wk.p, wk.q, wk.seed, args.mcs, 24)
+        print(json.dumps({"path": wk.name, "mcs": args.mcs, "ms": pms,
+                          "value": wk.sites * args.mcs / (pms / 1e3)}), flush=True)
         return
 
     if args.ensemble_only:
@@ -317,37 +401,31 @@ def main():
 
     w = HEADLINE
     K, Wm = args.steps, args.warmup
-    # The sweep runs as temporally blocked passes of DEPTH MCS each (all
-    # 26 half-steps of thirteen MCS in one sweep over the state, BAND-row
-    # bands per workgroup), an even number of passes per call; the MCS left
-    # over run as two shallower passes.  Every pass reads the packed state once
-    # and writes it once: X*Y/4 bytes each way.
-    DEPTH, BAND = 13, 256
-    n_pass = (K // DEPTH) & ~1
-    n_fused = n_pass * DEPTH
-    torch.cuda.synchronize()
-    if 0 < n_fused < K:
-        ms, fused_ms = time_path(torch, P, w.X, w.Y, w.p, w.q, w.seed, K, Wm, split=n_fused,
-                                 blocking=(DEPTH, BAND))
-    else:
-        ms = time_path(torch, P, w.X, w.Y, w.p, w.q, w.seed, K, Wm, blocking=(DEPTH, BAND))
-        fused_ms = ms
-    value = w.sites * K / (ms / 1e3)
+    hb = bench_headline(torch, P, w, K, Wm)
+    ms = hb["ms"]
+    plan = hb["plan"]
+    value = w.sites * w.n_mcs * K / (ms / 1e3)
+    # the dominant kernel: the whole blocked passes, state read once and
+    # written once per launch (X*Y/4 bytes each way)
     alg_bytes = w.sites // 2
-    if n_pass:
-        avg_ms = fused_ms / n_pass
-        kernel = f"mcs_fixed_kernel<8,{DEPTH},1,false>"
-        per_update = alg_bytes / (w.sites * DEPTH)
-    else:
-        avg_ms = ms / (2 * K)
-        kernel = "halfstep_kernel<64,8,Mask,false>"
-        per_update = alg_bytes / w.sites
-    pc = _pass_counters() if n_pass else {}
+    launches = plan["n_pass"] * K
+    avg_ms = hb["pass_ms"] / launches
+    pc = _pass_counters()
+    # counters taken on another kernel (or another instantiation) do not apply
+    if pc and plan["kernel"] not in pc.get("kernel", "").replace(" ", ""):
+        pc = {}
     roofline = pass_roofline(alg_bytes, avg_ms, pc)
-    roofline.update({"kernel": kernel,
-                     "alg_bytes_per_launch": alg_bytes, "mcs_per_launch": DEPTH if n_pass else 0.5,
-                     "alg_bytes_per_site_update": per_update, "avg_launch_ms": round(avg_ms, 5),
-                     "launches_timed": n_pass if n_pass else 2 * K})
+    roofline.update({
+        "kernel": plan["kernel"], "launches_timed": launches, "launches_per_step": plan["n_pass"],
+        "mcs_per_launch": plan["depth"], "band_rows": plan["band"], "alg_bytes_per_launch": alg_bytes,
+        "alg_bytes_per_site_update": alg_bytes / (w.sites * plan["depth"]), "avg_launch_ms": round(avg_ms, 5),
+        "share_of_step_time": round(hb["pass_ms"] / ms, 4),
+        "remainder": {"kernel": plan["tail_kernel"], "mcs": [plan["tail1"], plan["tail2"]]},
+        # the paper's bandwidth model (Sec. III): 1 byte per site update, one
+        # pass over the state per half-step; here a pass covers 2*depth half-steps
+        "paper_model_1B_per_update": {"equivalent_GBps": round(value / 1e9, 1),
+                                      "note": "site updates/s x 1 B; not HBM traffic"},
+    })
 
     out = {
         "metric": "site updates/s (bit-vectorized + arbitrary-p) vs HBM roofline; batched vs solo",
@@ -355,8 +433,9 @@ def main():
         "ms_per_step": ms / K, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u64", "data": "synthetic (flat initial surface)",
         "config": {"workload": w.name, "X": w.X, "Y": w.Y, "p": w.p, "q": w.q, "seed": w.seed,
-                   "mcs_per_step": 1},
+                   "mcs_per_step": w.n_mcs, "step": "flat init + 2000 MCS + exact moments"},
         "roofline": roofline,
+        "closed_form_holds": hb["closed_form_holds"],
     }
 
     if not args.no_paths:

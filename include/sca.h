@@ -31,11 +31,13 @@
  *
  * Conventions for every call:
  *  - Sizes: X and Y powers of two, 4 <= X, Y <= 131072.  0 <= p, q <= 1.
- *  - Ownership: every device buffer is owned by the caller; the library keeps
- *    non-owning pointers, so the caller keeps them alive until sca_destroy.
- *    The library owns a small device workspace (about 40*Y bytes)
- *    allocated by sca_init and, once the fused pass is first used, a second
- *    state buffer of the size of S; sca_destroy frees both.
+ *  - Ownership: every device buffer of state is owned by the caller: S, aux
+ *    and, for the temporally blocked passes, a second buffer of the size of
+ *    S (sca_set_pass_buffer).  The library keeps non-owning pointers, so the
+ *    caller keeps them alive until sca_destroy.  The library owns only a
+ *    small device workspace for the moment sums (about 32*Y bytes),
+ *    allocated by sca_init and freed by sca_destroy; sca_step allocates
+ *    nothing.
  *  - Streams: all work is enqueued on the stream given to sca_init.  Only
  *    calls that return numbers to the host synchronize that stream.
  *  - Errors: functions return SCA_OK or a negative code; an invalid argument
@@ -62,7 +64,10 @@ enum sca_status {
     SCA_EDEVICE = -3,   /* a HIP call failed; the context is now failed */
     SCA_EOVERFLOW = -4, /* an exact result does not fit its output type */
     SCA_ESTATE = -5,    /* the context failed earlier */
-    SCA_EBUSY = -6      /* a capacity limit was reached (batched calls) */
+    SCA_EBUSY = -6,     /* a capacity limit was reached (batched calls) */
+    SCA_ENOBUF = -7     /* a temporally blocked pass was planned but no pass
+                           buffer is attached (sca_set_pass_buffer); nothing
+                           was changed */
 };
 
 /* sca_step_ex flags */
@@ -90,15 +95,17 @@ int sca_init(sca_ctx** out, int64_t X, int64_t Y, uint64_t seed, void* slopes_de
 /* Advances n_mcs >= 0 MCS with deposition probability p and removal
  * probability q (Eq. (2)); each MCS is the even then the odd half-step
  * (Sec. I-A), t grows by n_mcs.  Asynchronous.
- * For X >= 8192 groups of MCS run as fused passes (all half-steps of
- * `depth` MCS in one sweep over the state, out of place into the library's
- * second buffer and back; see sca_set_blocking), which divides the HBM
- * traffic per MCS by about 2*depth.  The passes come in an even number so
- * that S holds the state when the enqueued work has run: whole passes of
- * `depth` MCS, then the remainder r as two passes of ceil(r/2) and
- * floor(r/2) MCS, or two half-step launches when r = 1.  The results are
- * bit-identical to the two-launch form.  If the second buffer cannot be
- * allocated the call falls back to two launches per MCS. */
+ * For X >= 8192 groups of MCS run as temporally blocked passes (all
+ * half-steps of `depth` MCS in one sweep over the state, out of place into
+ * the caller's pass buffer and back; see sca_set_blocking and
+ * sca_set_pass_buffer), which divides the HBM traffic per MCS by about
+ * 2*depth.  The passes come in an even number so that S holds the state when
+ * the enqueued work has run: whole passes of `depth` MCS, then the remainder
+ * r as two passes of ceil(r/2) and floor(r/2) MCS, or two half-step launches
+ * when r = 1 (sca_plan_step reports the plan).  The results are bit-identical
+ * to the two-launch form.  SCA_ENOBUF (nothing enqueued, t unchanged) if a
+ * blocked pass is planned and no pass buffer is attached; sca_set_blocking
+ * with depth 0 selects the two-launch form, which needs none. */
 int sca_step(sca_ctx* ctx, int64_t n_mcs, double p, double q);
 
 /* sca_step with flags (SCA_FORCE_PERSITE, SCA_STEP_GRAPH).  With
@@ -106,6 +113,54 @@ int sca_step(sca_ctx* ctx, int64_t n_mcs, double p, double q);
  * that is launched once (one launch for the whole run) and then released;
  * this call then synchronizes the stream. */
 int sca_step_ex(sca_ctx* ctx, int64_t n_mcs, double p, double q, unsigned flags);
+
+/* Acceptance paths (Sec. III and Sec. II-B): p and q both 0 or 1 (no random
+ * words), dyadic p and q (and/or fold of 64-bit draws), any other p or q (one
+ * 32-bit uniform per site). */
+#define SCA_PATH_DRAWFREE 0
+#define SCA_PATH_MASK 1
+#define SCA_PATH_PERSITE 2
+
+/* The launches sca_step_ex(ctx, n_mcs, p, q, flags) would enqueue with the
+ * context's current blocking settings. */
+typedef struct sca_step_plan {
+    int32_t path;          /* SCA_PATH_* */
+    int32_t depth;         /* MCS per whole blocked pass; 0 if there is none */
+    int32_t band;          /* rows per workgroup band of a blocked pass */
+    int32_t tail1, tail2;  /* MCS of the two remainder passes; 0 if none */
+    int64_t n_pass;        /* whole passes of `depth` MCS (even) */
+    int64_t n_unfused;     /* MCS run as two half-step launches each */
+    char kernel[80];       /* kernel of the whole passes, with its template
+                              arguments, or "none" */
+    char tail_kernel[80];  /* kernel of the first remainder pass, or "none" */
+    char halfstep_kernel[80]; /* kernel of a half-step launch */
+} sca_step_plan;
+
+/* Fills *out with the plan of sca_step_ex for these arguments (host only, no
+ * device work).  SCA_EINVAL for invalid arguments. */
+int sca_plan_step(const sca_ctx* ctx, int64_t n_mcs, double p, double q, unsigned flags, sca_step_plan* out);
+
+/* Attaches the caller-owned device buffer pass_dev of `bytes` bytes, at least
+ * 8 * sca_state_words(X, Y), that the temporally blocked passes write every
+ * other pass (a pass reads beyond its bands, so it runs out of place).  It
+ * must not overlap S.  Its contents between calls are meaningless.  NULL
+ * detaches it.  SCA_EINVAL if too small or overlapping. */
+int sca_set_pass_buffer(sca_ctx* ctx, void* pass_dev, size_t bytes);
+
+/* Writes the flat initial surface into S again (as sca_init does): h(0,0) = 0,
+ * t = 0.  Asynchronous. */
+int sca_reset(sca_ctx* ctx);
+
+/* Restores a state saved by sca_snapshot (or written in its layout: S, then
+ * one int64 h(0,0)) from the caller-owned device buffer snap_dev into S and
+ * aux[0], and sets the MCS counter to t, 0 <= t < 2^32.  The random stream is
+ * counter-based (MCS index, half-step, draw, word), so its whole state is t:
+ * a run resumed at t continues bit-identically (the paper loads and stores
+ * its generator states around the update loop, Fig. 3).  The buffer must hold
+ * a valid surface (every bond a slope of +-1; per row X/2 up x-slopes and per
+ * column Y/2 up y-slopes as on every surface reached from the flat one);
+ * unused bits of partial words (X < 128) must be zero.  Asynchronous. */
+int sca_restore(sca_ctx* ctx, const void* snap_dev, int64_t t);
 
 /* Heights h(x,y) of rows [y0, y0+ny), all x, row-major int32 into out_dev
  * (ny*X values, caller-owned):
@@ -152,8 +207,8 @@ int sca_get_meta(sca_ctx* ctx, int64_t* t, int64_t* h0);
  * Any setting gives bit-identical results. */
 int sca_set_blocking(sca_ctx* ctx, int32_t depth, int32_t band);
 
-/* Sets the MCS counter (for resuming from a saved state; the caller restores
- * S and aux itself).  0 <= t < 2^32. */
+/* Sets the MCS counter (sca_restore sets it together with the state).
+ * 0 <= t < 2^32. */
 int sca_set_time(sca_ctx* ctx, int64_t t);
 
 /* Test hook: one half-step of sublattice `parity` whose acceptance words are

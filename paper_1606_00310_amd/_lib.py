@@ -13,11 +13,12 @@ import torch  # noqa: F401  (loads the HIP runtime the library links against)
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsca.so")
 
-SCA_OK, SCA_EINVAL, SCA_ENOMEM, SCA_EDEVICE, SCA_EOVERFLOW, SCA_ESTATE, SCA_EBUSY = 0, -1, -2, -3, -4, -5, -6
+SCA_OK, SCA_EINVAL, SCA_ENOMEM, SCA_EDEVICE, SCA_EOVERFLOW, SCA_ESTATE, SCA_EBUSY, SCA_ENOBUF = 0, -1, -2, -3, -4, -5, -6, -7
 SCA_FORCE_PERSITE = 1
 SCA_STEP_GRAPH = 2
 SCA_NO_FUSE = 4
 SCA_AUX_LEN = 8
+SCA_PATH_DRAWFREE, SCA_PATH_MASK, SCA_PATH_PERSITE = 0, 1, 2
 
 
 class ScaError(RuntimeError):
@@ -41,6 +42,18 @@ class BatchConfig(ctypes.Structure):
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+class StepPlan(ctypes.Structure):
+    """sca_step_plan: the launches sca_step_ex would enqueue."""
+    _fields_ = [("path", ctypes.c_int32), ("depth", ctypes.c_int32), ("band", ctypes.c_int32),
+                ("tail1", ctypes.c_int32), ("tail2", ctypes.c_int32), ("n_pass", ctypes.c_int64),
+                ("n_unfused", ctypes.c_int64), ("kernel", ctypes.c_char * 80), ("tail_kernel", ctypes.c_char * 80),
+                ("halfstep_kernel", ctypes.c_char * 80)]
+
+    def as_dict(self):
+        return {f: (getattr(self, f).decode() if isinstance(getattr(self, f), bytes) else int(getattr(self, f)))
+                for f, _ in self._fields_}
 
 
 class SlotInfo(ctypes.Structure):
@@ -67,6 +80,10 @@ _SIGNATURES = {
     "sca_autocorr": ([_vp, _vp, _i64p, _dblp], _int),
     "sca_get_meta": ([_vp, _i64p, _i64p], _int),
     "sca_set_time": ([_vp, _i64], _int),
+    "sca_plan_step": ([_vp, _i64, _dbl, _dbl, ctypes.c_uint, ctypes.POINTER(StepPlan)], _int),
+    "sca_set_pass_buffer": ([_vp, _vp, ctypes.c_size_t], _int),
+    "sca_reset": ([_vp], _int),
+    "sca_restore": ([_vp, _vp, _i64], _int),
     "sca_set_blocking": ([_vp, ctypes.c_int32, ctypes.c_int32], _int),
     "sca_debug_halfstep": ([_vp, _int, _vp, _vp], _int),
     "sca_debug_philox": ([_vp, _u32, _u32, _i64, _vp, _vp], _int),

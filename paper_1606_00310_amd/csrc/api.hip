@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <algorithm>
 #include <map>
@@ -31,7 +32,7 @@ struct sca_ctx {
     bool failed = false;
     int64_t* ws = nullptr;     // library-owned: rows[3Y], col[Y], res[8]
     hipStream_t capture = nullptr;  // private stream for hipGraph capture (created on first use)
-    uint64_t* alt = nullptr;        // library-owned second state for the fused passes (first use)
+    uint64_t* alt = nullptr;        // caller-owned second state for the blocked passes (sca_set_pass_buffer)
     int32_t depth = -1;             // MCS per fused pass; -1 = automatic, 0 = never fuse
     int32_t band = 0;               // rows per workgroup in a fused pass; 0 = automatic
 };
@@ -162,6 +163,96 @@ hipError_t run_as_graph(hipStream_t& capture, hipStream_t stream, F enqueue)
     return e != hipSuccess ? e : es;
 }
 
+// What sca_step_ex runs for n_mcs MCS at (p, q): the acceptance path and the
+// pass plan.  Groups of `depth` MCS run as fused passes alternating
+// S -> pass buffer -> S (one HBM pass per group); the number of passes is
+// kept even so that the caller's S holds the state after the call: an even
+// number of `depth`-MCS passes, then the remainder r < 2*depth as two passes
+// of ceil(r/2) and floor(r/2) MCS, or, for r = 1, two half-step launches.
+// Automatic choice: a band per workgroup with enough waves to fill the chip
+// and bands as tall as that allows; deep passes on tall bands (the halo costs
+// 4*depth rows per band), shallower ones on short bands.  The per-site path
+// is ALU-bound and runs unfused.
+struct StepPlan {
+    ProbCode P, Q;
+    bool persite = false, has_q = false, draw_free = false;
+    sca::XiMode mode = sca::XiMode::Mask;
+    int32_t ndraw = 0;
+    int32_t band = 0, depth = 0;
+    int64_t n_pass = 0;
+    int32_t tail1 = 0, tail2 = 0;
+};
+
+StepPlan make_plan(const sca_ctx* c, int64_t n_mcs, double p, double q, unsigned flags)
+{
+    StepPlan pl;
+    pl.P = classify(p);
+    pl.Q = classify(q);
+    pl.persite = (flags & SCA_FORCE_PERSITE) || !pl.P.dyadic || !pl.Q.dyadic;
+    pl.has_q = (q > 0.0);
+    pl.mode = pl.persite ? sca::XiMode::PerSite : sca::XiMode::Mask;
+    pl.ndraw = pl.persite ? 0 : (pl.P.n > pl.Q.n ? pl.P.n : pl.Q.n);
+    const int64_t nw = c->W >= 512 ? 8 : (c->W >= 64 ? c->W / 64 : 1);
+    // Without random words (p, q in {0, 1}) a pass costs little more than
+    // a shallower one as long as its window fits the registers: 13 MCS at
+    // X = 2^16 and 8 below (the register-window kernels), 6 at X = 2^17 (the
+    // LDS-window kernel with 1024-thread workgroups), on bands of up to 256
+    // rows (about one workgroup per CU); passes with draws are ALU-bound and
+    // do best at 4 MCS on bands of up to 128 rows.
+    pl.draw_free = !pl.persite && pl.ndraw == 0;
+    int32_t band = c->band;
+    if (band == 0) {
+        int64_t b = pl.draw_free ? 256 : 128;
+        while (b > 8 && c->Y / b < 2048 / nw) b >>= 1;
+        band = (int32_t)b;
+    }
+    pl.band = band;
+    const int32_t dmax = sca::max_fused_depth(c->W, pl.mode, pl.ndraw);
+    int32_t depth = c->depth;
+    if (depth < 0) {
+        depth = pl.persite ? 0
+                           : band >= 256 ? (pl.draw_free ? 13 : 4)
+                           : band >= 128 ? (pl.draw_free ? 10 : 4)
+                           : band >= 64 ? (pl.draw_free ? 5 : 3)
+                           : band >= 32 ? 3
+                           : band >= 16 ? 2
+                                        : 1;
+    }
+    if (depth > dmax) depth = dmax;
+    pl.depth = depth;
+    const bool fuse = !(flags & SCA_NO_FUSE) && depth > 0 && n_mcs >= 2 &&
+                      sca::fused_supported(c->W, c->Y, band, depth, pl.mode, pl.ndraw);
+    pl.n_pass = fuse ? ((n_mcs / depth) & ~(int64_t)1) : 0;
+    const int64_t rem = n_mcs - pl.n_pass * depth;
+    pl.tail1 = (fuse && rem >= 2) ? (int32_t)((rem + 1) / 2) : 0;
+    pl.tail2 = (fuse && rem >= 2) ? (int32_t)(rem / 2) : 0;
+    return pl;
+}
+
+sca::SweepArgs sweep_args(const sca_ctx* c, const StepPlan& pl)
+{
+    sca::SweepArgs a{};
+    a.S = c->S;
+    a.plane = c->Y * c->W;
+    a.W = c->W;
+    a.Y = (int32_t)c->Y;
+    a.nb = c->nb;
+    a.k0 = (uint32_t)c->seed;
+    a.k1 = (uint32_t)(c->seed >> 32);
+    a.h0 = c->aux;
+    a.all_p = pl.P.all;
+    a.all_q = pl.Q.all;
+    if (pl.persite) {
+        a.thr_p = pl.P.thr;
+        a.thr_q = pl.Q.thr;
+    } else {
+        a.dig_p = pl.P.digits;
+        a.dig_q = pl.Q.digits;
+        a.ndraw = pl.ndraw;
+    }
+    return a;
+}
+
 }  // namespace
 
 extern "C" {
@@ -182,6 +273,7 @@ const char* sca_strerror(int code)
     case SCA_EOVERFLOW: return "exact result does not fit its output type";
     case SCA_ESTATE: return "context failed earlier";
     case SCA_EBUSY: return "capacity limit reached";
+    case SCA_ENOBUF: return "a blocked pass needs the caller's pass buffer (sca_set_pass_buffer)";
     default: return "unknown status";
     }
 }
@@ -225,100 +317,30 @@ int sca_step_ex(sca_ctx* c, int64_t n_mcs, double p, double q, unsigned flags)
         return SCA_EINVAL;
     if (c->t + n_mcs > (int64_t)UINT32_MAX) return SCA_EINVAL;
     if (n_mcs == 0) return SCA_OK;
+    const StepPlan pl = make_plan(c, n_mcs, p, q, flags);
+    // the blocked passes alternate between S and the caller's pass buffer
+    if (pl.n_pass + (pl.tail1 ? 2 : 0) > 0 && !c->alt) return SCA_ENOBUF;
     DeviceGuard dg(c->device);
     if (!dg.ok) return fail(c);
 
-    const ProbCode P = classify(p), Q = classify(q);
-    const bool persite = (flags & SCA_FORCE_PERSITE) || !P.dyadic || !Q.dyadic;
-    const bool has_q = (q > 0.0);
-    sca::SweepArgs a{};
-    a.S = c->S;
-    a.plane = c->Y * c->W;
-    a.W = c->W;
-    a.Y = (int32_t)c->Y;
-    a.nb = c->nb;
-    a.k0 = (uint32_t)c->seed;
-    a.k1 = (uint32_t)(c->seed >> 32);
-    a.h0 = c->aux;
-    a.all_p = P.all;
-    a.all_q = Q.all;
-    if (persite) {
-        a.thr_p = P.thr;
-        a.thr_q = Q.thr;
-    } else {
-        a.dig_p = P.digits;
-        a.dig_q = Q.digits;
-        a.ndraw = P.n > Q.n ? P.n : Q.n;
-    }
-    const sca::XiMode mode = persite ? sca::XiMode::PerSite : sca::XiMode::Mask;
+    sca::SweepArgs a = sweep_args(c, pl);
     const int64_t t0 = c->t;
-    // Groups of `depth` MCS run as fused passes alternating S -> alt -> S (one
-    // HBM pass per group); the number of passes is kept even so that the
-    // caller's S holds the state after the call (see the remainder below).
-    // Automatic choice: a band per workgroup with enough waves to fill the
-    // chip and bands as tall as that allows; deep passes on tall bands (the
-    // halo costs 4*depth rows per band), shallower ones on short bands.  The
-    // per-site path is ALU-bound and runs unfused.
-    const int64_t nw = c->W >= 512 ? 8 : (c->W >= 64 ? c->W / 64 : 1);
-    // Without random words (p, q in {0, 1}) a pass costs little more than
-    // a shallower one as long as its window fits the registers: 13 MCS at
-    // X = 2^16 and 8 below (the register-window kernels), 6 at X = 2^17 (the
-    // LDS-window kernel with 1024-thread workgroups), on bands of up to 256
-    // rows (about one workgroup per CU); passes with draws are ALU-bound and
-    // do best at 4 MCS on bands of up to 128 rows.
-    const bool draw_free = !persite && a.ndraw == 0;
-    int32_t band = c->band;
-    if (band == 0) {
-        int64_t b = draw_free ? 256 : 128;
-        while (b > 8 && c->Y / b < 2048 / nw) b >>= 1;
-        band = (int32_t)b;
-    }
-    const int32_t dmax = sca::max_fused_depth(c->W, mode, a.ndraw);
-    int32_t depth = c->depth;
-    if (depth < 0) {
-        depth = persite ? 0
-                        : band >= 256 ? (draw_free ? 13 : 4)
-                        : band >= 128 ? (draw_free ? 10 : 4)
-                        : band >= 64 ? (draw_free ? 5 : 3)
-                        : band >= 32 ? 3
-                        : band >= 16 ? 2
-                                     : 1;
-    }
-    if (depth > dmax) {
-        depth = dmax;
-    }
-    bool fuse = !(flags & SCA_NO_FUSE) && depth > 0 && n_mcs >= 2 &&
-                sca::fused_supported(c->W, c->Y, band, depth, mode, a.ndraw);
-    if (fuse && !c->alt) {
-        if (hipMalloc(&c->alt, sizeof(uint64_t) * (size_t)(4 * c->Y * c->W)) != hipSuccess) {
-            (void)hipGetLastError();
-            c->alt = nullptr;
-            fuse = false;  // not enough memory for the second state: unfused launches
-        }
-    }
-    // An even number of `depth`-MCS passes, then the remainder r < 2*depth as
-    // two passes of ceil(r/2) and floor(r/2) MCS (still an even count), or, for
-    // r = 1, as two half-step launches.
-    const int64_t n_pass = fuse ? ((n_mcs / depth) & ~(int64_t)1) : 0;
-    const int64_t rem = n_mcs - n_pass * depth;
-    const int32_t tail1 = (fuse && rem >= 2) ? (int32_t)((rem + 1) / 2) : 0;
-    const int32_t tail2 = (fuse && rem >= 2) ? (int32_t)(rem / 2) : 0;
-    const int64_t n_fused = n_pass * depth + tail1 + tail2;
+    const int64_t n_fused = pl.n_pass * pl.depth + pl.tail1 + pl.tail2;
     auto enqueue = [&](hipStream_t st) -> hipError_t {
-        for (int64_t i = 0; i < n_pass + (tail1 ? 2 : 0); ++i) {
-            const bool tail = i >= n_pass;
-            const int32_t d = !tail ? depth : (i == n_pass ? tail1 : tail2);
-            a.t = (uint32_t)(t0 + (!tail ? i * depth : n_pass * depth + (i == n_pass ? 0 : tail1)));
+        for (int64_t i = 0; i < pl.n_pass + (pl.tail1 ? 2 : 0); ++i) {
+            const bool tail = i >= pl.n_pass;
+            const int32_t d = !tail ? pl.depth : (i == pl.n_pass ? pl.tail1 : pl.tail2);
+            a.t = (uint32_t)(t0 + (!tail ? i * pl.depth : pl.n_pass * pl.depth + (i == pl.n_pass ? 0 : pl.tail1)));
             const bool fwd = (i & 1) == 0;
-            const hipError_t e = sca::launch_mcs_fused(a, mode, has_q, fwd ? c->S : c->alt, fwd ? c->alt : c->S,
-                                                       band, d, st);
+            const hipError_t e = sca::launch_mcs_fused(a, pl.mode, pl.has_q, fwd ? c->S : c->alt,
+                                                       fwd ? c->alt : c->S, pl.band, d, st);
             if (e != hipSuccess) return e;
         }
         for (int64_t i = n_fused; i < n_mcs; ++i) {
             a.t = (uint32_t)(t0 + i);
             for (int parity = 0; parity < 2; ++parity) {
                 a.parity = parity;
-                const hipError_t e = sca::launch_halfstep(a, mode, has_q, st);
+                const hipError_t e = sca::launch_halfstep(a, pl.mode, pl.has_q, st);
                 if (e != hipSuccess) return e;
             }
         }
@@ -327,6 +349,71 @@ int sca_step_ex(sca_ctx* c, int64_t n_mcs, double p, double q, unsigned flags)
     const hipError_t e = (flags & SCA_STEP_GRAPH) ? run_as_graph(c->capture, c->stream, enqueue) : enqueue(c->stream);
     if (e != hipSuccess) return fail(c);
     c->t += n_mcs;
+    return SCA_OK;
+}
+
+int sca_plan_step(const sca_ctx* c, int64_t n_mcs, double p, double q, unsigned flags, sca_step_plan* out)
+{
+    if (!c || !out || n_mcs < 0 || !valid_prob(p) || !valid_prob(q) ||
+        (flags & ~(SCA_FORCE_PERSITE | SCA_STEP_GRAPH | SCA_NO_FUSE)))
+        return SCA_EINVAL;
+    const StepPlan pl = make_plan(c, n_mcs, p, q, flags);
+    std::memset(out, 0, sizeof *out);
+    out->path = pl.persite ? SCA_PATH_PERSITE : (pl.draw_free ? SCA_PATH_DRAWFREE : SCA_PATH_MASK);
+    out->band = pl.band;
+    out->n_pass = pl.n_pass;
+    out->depth = pl.n_pass > 0 ? pl.depth : 0;
+    out->tail1 = pl.tail1;
+    out->tail2 = pl.tail2;
+    out->n_unfused = n_mcs - (pl.n_pass * pl.depth + pl.tail1 + pl.tail2);
+    const sca::SweepArgs a = sweep_args(c, pl);
+    if (pl.n_pass > 0) sca::fused_kernel_name(a, pl.mode, pl.has_q, pl.depth, out->kernel, sizeof out->kernel);
+    else std::snprintf(out->kernel, sizeof out->kernel, "none");
+    if (pl.tail1) sca::fused_kernel_name(a, pl.mode, pl.has_q, pl.tail1, out->tail_kernel, sizeof out->tail_kernel);
+    else std::snprintf(out->tail_kernel, sizeof out->tail_kernel, "none");
+    sca::halfstep_kernel_name(c->W, pl.mode, pl.has_q, out->halfstep_kernel, sizeof out->halfstep_kernel);
+    return SCA_OK;
+}
+
+int sca_set_pass_buffer(sca_ctx* c, void* pass_dev, size_t bytes)
+{
+    if (!c) return SCA_EINVAL;
+    if (c->failed) return SCA_ESTATE;
+    const size_t need = sizeof(uint64_t) * (size_t)(4 * c->Y * c->W);
+    if (!pass_dev) {
+        c->alt = nullptr;
+        return SCA_OK;
+    }
+    const uintptr_t a0 = (uintptr_t)pass_dev, s0 = (uintptr_t)c->S;
+    if (bytes < need || (pass_dev && a0 < s0 + need && s0 < a0 + need)) return SCA_EINVAL;
+    c->alt = static_cast<uint64_t*>(pass_dev);
+    return SCA_OK;
+}
+
+int sca_reset(sca_ctx* c)
+{
+    if (!c) return SCA_EINVAL;
+    if (c->failed) return SCA_ESTATE;
+    DeviceGuard dg(c->device);
+    if (!dg.ok) return fail(c);
+    if (sca::launch_flat_init(c->S, c->Y, c->W, c->nb, c->aux, c->stream) != hipSuccess) return fail(c);
+    c->t = 0;
+    return SCA_OK;
+}
+
+int sca_restore(sca_ctx* c, const void* snap_dev, int64_t t)
+{
+    if (!c || !snap_dev || t < 0 || t > (int64_t)UINT32_MAX) return SCA_EINVAL;
+    if (c->failed) return SCA_ESTATE;
+    DeviceGuard dg(c->device);
+    if (!dg.ok) return fail(c);
+    const size_t words = (size_t)(4 * c->Y * c->W);
+    const uint64_t* src = static_cast<const uint64_t*>(snap_dev);
+    if (hipMemcpyAsync(c->S, src, words * sizeof(uint64_t), hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+        return fail(c);
+    if (hipMemcpyAsync(c->aux, src + words, sizeof(int64_t), hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+        return fail(c);
+    c->t = t;
     return SCA_OK;
 }
 
@@ -490,7 +577,6 @@ void sca_destroy(sca_ctx* c)
         (void)hipStreamSynchronize(c->stream);
         (void)hipFree(c->ws);
         if (c->capture) (void)hipStreamDestroy(c->capture);
-        if (c->alt) (void)hipFree(c->alt);
     }
     delete c;
 }
@@ -609,6 +695,11 @@ struct sca_batch {
     int32_t* h_count = nullptr;
     hipEvent_t staged = nullptr;
     bool staged_pending = false;
+    // flat initialisation of admitted realizations: one launch per admission
+    sca::FlatItem* h_flat = nullptr;  // pinned staging
+    sca::FlatItem* d_flat = nullptr;
+    hipEvent_t flat_staged = nullptr;
+    bool flat_pending = false;
     hipGraphExec_t exec = nullptr;
     bool failed = false;
 };
@@ -625,6 +716,9 @@ void batch_free(sca_batch* b)
 {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->staged) (void)hipEventDestroy(b->staged);
+    if (b->flat_staged) (void)hipEventDestroy(b->flat_staged);
+    (void)hipFree(b->d_flat);
+    (void)hipHostFree(b->h_flat);
     if (b->capture) (void)hipStreamDestroy(b->capture);
     (void)hipFree(b->d_desc);
     (void)hipFree(b->d_order);
@@ -722,7 +816,10 @@ int sca_batch_create(sca_batch** out, int32_t max_slots, void* arena_dev, size_t
         hipHostMalloc(&b->h_desc, nd, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(&b->h_order, no, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(&b->h_count, sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
-        hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) != hipSuccess ||
+        hipMalloc(&b->d_flat, sizeof(sca::FlatItem) * (size_t)max_slots) != hipSuccess ||
+        hipHostMalloc(&b->h_flat, sizeof(sca::FlatItem) * (size_t)max_slots, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&b->flat_staged, hipEventDisableTiming) != hipSuccess) {
         (void)hipGetLastError();
         batch_free(b);
         return SCA_ENOMEM;
@@ -779,6 +876,10 @@ int sca_batch_admit(sca_batch* b, const sca_req* reqs, int32_t n, int32_t* slots
     }
     DeviceGuard dg(b->device);
     if (!dg.ok) return bfail(b);
+    // the flat-init staging is free once the previous admission's copy has run
+    if (b->flat_pending && hipEventSynchronize(b->flat_staged) != hipSuccess) return bfail(b);
+    b->flat_pending = false;
+    int32_t n_flat = 0;
     for (int32_t i = 0; i < n; ++i) {
         const sca_req& r = reqs[i];
         const int32_t slot = b->free_slots.back();
@@ -815,8 +916,22 @@ int sca_batch_admit(sca_batch* b, const sca_req* reqs, int32_t n, int32_t* slots
             d.dig_q = Q.digits;
             d.ndraw = P.n > Q.n ? P.n : Q.n;
         }
-        if (sca::launch_flat_init(d.S, r.Y, s.W, s.nb, d.h0, b->stream) != hipSuccess) return bfail(b);
+        // states of up to 2^20 words share one launch (one workgroup per
+        // state); larger ones get a launch of their own
+        if (4 * d.plane <= ((int64_t)1 << 20)) {
+            b->h_flat[n_flat++] = sca::flat_item(d.S, r.Y, s.W, s.nb, d.h0);
+        } else if (sca::launch_flat_init(d.S, r.Y, s.W, s.nb, d.h0, b->stream) != hipSuccess) {
+            return bfail(b);
+        }
         slots_out[i] = slot;
+    }
+    if (n_flat > 0) {
+        if (hipMemcpyAsync(b->d_flat, b->h_flat, sizeof(sca::FlatItem) * (size_t)n_flat, hipMemcpyHostToDevice,
+                           b->stream) != hipSuccess ||
+            hipEventRecord(b->flat_staged, b->stream) != hipSuccess ||
+            sca::launch_flat_init_many(b->d_flat, n_flat, b->stream) != hipSuccess)
+            return bfail(b);
+        b->flat_pending = true;
     }
     return SCA_OK;
 }

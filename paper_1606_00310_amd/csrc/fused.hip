@@ -1,6 +1,8 @@
 // fused.hip -- dispatch of the temporally blocked passes (kernels in fused.hpp);
 // passes of 1..4 MCS are instantiated here, 5..8 in fused_deep.hip and 9..12
 // (X = 2^16) in fused_deeper.hip.
+#include <cstdio>
+
 #include "fused.hpp"
 
 namespace sca {
@@ -41,6 +43,33 @@ hipError_t launch_mcs_fused(const SweepArgs& a, XiMode mode, bool has_q, const u
     case 4: return launch_depth<4>(a, mode, has_q, src, dst, band, stream);
     default: return launch_mcs_fused_deep(a, mode, has_q, src, dst, band, depth, stream);
     }
+}
+
+// The same choices as launch_depth, launch_block (fused.hpp) and
+// launch_fixed512 (fused_deeper.hip), spelled out as the kernel's name.
+void fused_kernel_name(const SweepArgs& a, XiMode mode, bool has_q, int32_t depth, char* out, size_t n)
+{
+    const char* q = has_q ? "true" : "false";
+    // the draw-free register-window kernels take the general masks unless p = 1, q = 0
+    const char* gq = (has_q || a.all_p == 0) ? "true" : "false";
+    const bool draw_free = mode == XiMode::Mask && a.ndraw == 0;
+    const char* m = mode == XiMode::PerSite ? "PerSite" : (draw_free ? "Fixed" : "Mask");
+    if (depth < 1) {
+        std::snprintf(out, n, "none");
+        return;
+    }
+    if (a.W == 1024) {
+        if (depth == kLdsDepth && draw_free) std::snprintf(out, n, "mcs_block_lds_kernel<16,%d,%s>", depth, q);
+        else std::snprintf(out, n, "mcs_block_kernel<8,2,%d,%s,%s>", depth, m, q);
+        return;
+    }
+    const int nw = a.W / 64;
+    if (draw_free && depth >= kFixedDeepDepth)
+        std::snprintf(out, n, "mcs_fixed_kernel<%d,%d,%d,%s>", nw, depth, (depth >= 12 ? 1 : 3), gq);
+    else if (draw_free && depth >= kLdsDepth)
+        std::snprintf(out, n, "mcs_block_lds_kernel<%d,%d,%s>", nw, depth, q);
+    else
+        std::snprintf(out, n, "mcs_block_kernel<%d,1,%d,%s,%s>", nw, depth, m, q);
 }
 
 }  // namespace sca

@@ -31,6 +31,22 @@ __global__ void flat_init_kernel(uint64_t* S, int64_t plane, uint64_t valid, int
     if (blockIdx.x == 0 && threadIdx.x == 0) *h0 = 0;
 }
 
+// The flat surface for many lattices at once: workgroup i initialises items
+// i, i + gridDim.x, ... (their states are small: one admission of an
+// ensemble issues one launch instead of one per realization).
+__global__ __launch_bounds__(kBlock) void flat_init_many_kernel(const FlatItem* items, int32_t n)
+{
+    for (int32_t it = blockIdx.x; it < n; it += gridDim.x) {
+        const FlatItem f = items[it];
+        const int64_t words = 4 * f.plane;
+        for (int64_t i = threadIdx.x; i < words; i += kBlock) {
+            const int parity = (int)((i / f.plane) & 1);  // arrays ordered S[d][parity]
+            f.S[i] = parity ? f.valid : 0ull;
+        }
+        if (threadIdx.x == 0) *f.h0 = 0;
+    }
+}
+
 // Local sums of one word pair (even-x word E, odd-x word O) over its 2*nb
 // sites; the global site x = 0 contributes no step (skip0).
 struct WordSums {
@@ -343,6 +359,19 @@ hipError_t launch_flat_init(uint64_t* S, int64_t Y, int32_t W, int32_t nb, int64
     int64_t blocks = (4 * plane + kBlock - 1) / kBlock;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(flat_init_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, stream, S, plane, valid, h0);
+    return hipGetLastError();
+}
+
+FlatItem flat_item(uint64_t* S, int64_t Y, int32_t W, int32_t nb, int64_t* h0)
+{
+    return FlatItem{S, h0, Y * W, (nb == 64) ? ~0ull : ((1ull << nb) - 1ull)};
+}
+
+hipError_t launch_flat_init_many(const FlatItem* items_dev, int32_t n, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    const int32_t grid = n < 4096 ? n : 4096;
+    hipLaunchKernelGGL(flat_init_many_kernel, dim3((unsigned)grid), dim3(kBlock), 0, stream, items_dev, n);
     return hipGetLastError();
 }
 

@@ -21,9 +21,25 @@ bool fused_supported(int32_t W, int64_t Y, int32_t band, int32_t depth, XiMode m
 hipError_t launch_mcs_fused(const SweepArgs& a, XiMode mode, bool has_q, const uint64_t* src, uint64_t* dst,
                             int32_t band, int32_t depth, hipStream_t stream);
 
+// Name of the kernel (with its template arguments) that launch_mcs_fused and
+// launch_halfstep run for these arguments; written next to their dispatch.
+void fused_kernel_name(const SweepArgs& a, XiMode mode, bool has_q, int32_t depth, char* out, size_t n);
+void halfstep_kernel_name(int32_t W, XiMode mode, bool has_q, char* out, size_t n);
+
 // Flat initial surface into S and h0 = 0.
 hipError_t launch_flat_init(uint64_t* S, int64_t Y, int32_t W, int32_t nb, int64_t* h0,
                             hipStream_t stream);
+
+// The flat surface for a list of lattices in one launch (device table of
+// items); meant for small states such as an ensemble's realizations.
+struct FlatItem {
+    uint64_t* S;
+    int64_t* h0;
+    int64_t plane;   // Y*W
+    uint64_t valid;  // used bits of a word
+};
+FlatItem flat_item(uint64_t* S, int64_t Y, int32_t W, int32_t nb, int64_t* h0);
+hipError_t launch_flat_init_many(const FlatItem* items_dev, int32_t n, hipStream_t stream);
 
 // Per-row sums for the moments (and the two-time sums when snap != nullptr):
 // rows[y*3 + {0,1,2}] = {sum_x P_t, sum_x P_t^2 (or sum_x P_t P_s), sum_x P_s}

@@ -9,6 +9,8 @@
 // same rotation, Fig. 3), and the periodic wrap of the row (the paper caches
 // the first word separately, Sec. II-B) is a rotation of packed bits inside
 // the wave.  The arithmetic of a row group lives in halfstep.hpp.
+#include <cstdio>
+
 #include "halfstep.hpp"
 #include "sca_internal.hpp"
 
@@ -99,6 +101,14 @@ hipError_t launch_halfstep(const SweepArgs& a, XiMode mode, bool has_q, hipStrea
     case 1024: return launch_layout<64, 16>(a, mode, has_q, stream);
     default: return hipErrorInvalidValue;
     }
+}
+
+// The kernel launch_halfstep runs for rows of W words (see launch_layout).
+void halfstep_kernel_name(int32_t W, XiMode mode, bool has_q, char* out, size_t n)
+{
+    const int G = W < 64 ? W : 64, I = W < 64 ? 1 : W / 64;
+    const char* m = mode == XiMode::PerSite ? "PerSite" : (mode == XiMode::Inject ? "Inject" : "Mask");
+    std::snprintf(out, n, "halfstep_kernel<%d,%d,%s,%s>", G, I, m, (has_q || mode == XiMode::Inject) ? "true" : "false");
 }
 
 hipError_t launch_philox_test(const uint32_t* ctr, uint32_t k0, uint32_t k1, int64_t n, uint32_t* out,

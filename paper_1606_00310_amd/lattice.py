@@ -26,12 +26,18 @@ class Lattice:
         self.W = max(1, self.X // 128)
         self.slopes = torch.empty((2, 2, self.Y, self.W), dtype=torch.int64, device=self.device)
         self.aux = torch.zeros(L.SCA_AUX_LEN, dtype=torch.int64, device=self.device)
+        # the temporally blocked passes (X >= 8192) run out of place into a
+        # second buffer of the state's size
+        self.pass_buffer = torch.empty_like(self.slopes) if self.X >= 8192 else None
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         ctx = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             L.check(L.lib().sca_init(ctypes.byref(ctx), self.X, self.Y, self.seed, self.slopes.data_ptr(),
                                      self.aux.data_ptr(), self.stream.cuda_stream), "sca_init")
         self._ctx = ctx
+        if self.pass_buffer is not None:
+            L.check(L.lib().sca_set_pass_buffer(ctx, self.pass_buffer.data_ptr(),
+                                                self.pass_buffer.numel() * 8), "sca_set_pass_buffer")
 
     # ------------------------------------------------------------------ steps
     def step(self, n_mcs: int, p: float, q: float = 0.0, force_persite: bool = False, graph: bool = False,
@@ -43,6 +49,25 @@ class Lattice:
                  | (0 if fuse else L.SCA_NO_FUSE))
         L.check(L.lib().sca_step_ex(self._ctx, int(n_mcs), float(p), float(q), flags), "sca_step")
         return self
+
+    def plan(self, n_mcs: int, p: float, q: float = 0.0, force_persite: bool = False, fuse: bool = True) -> dict:
+        """The launches step() would enqueue (sca_plan_step)."""
+        flags = (L.SCA_FORCE_PERSITE if force_persite else 0) | (0 if fuse else L.SCA_NO_FUSE)
+        out = L.StepPlan()
+        L.check(L.lib().sca_plan_step(self._ctx, int(n_mcs), float(p), float(q), flags, ctypes.byref(out)),
+                "sca_plan_step")
+        return out.as_dict()
+
+    def reset(self):
+        """The flat initial surface again, t = 0."""
+        L.check(L.lib().sca_reset(self._ctx), "sca_reset")
+
+    def restore(self, snap: torch.Tensor, t: int):
+        """State and h(0,0) from a snapshot-layout tensor (S words, then h(0,0)), MCS counter t."""
+        if snap.numel() * 8 != L.lib().sca_snapshot_bytes(self._ctx) or snap.device != self.device \
+                or not snap.is_contiguous():
+            raise ValueError("snapshot of another lattice size or device")
+        L.check(L.lib().sca_restore(self._ctx, snap.data_ptr(), int(t)), "sca_restore")
 
     def debug_halfstep(self, parity: int, xi_p: torch.Tensor, xi_q: torch.Tensor):
         """Half-step with injected acceptance words (int64 tensors of Y*W words)."""

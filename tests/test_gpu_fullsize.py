@@ -115,32 +115,53 @@ def test_headline_half_windows(orc, sca):
     lat.close()
 
 
-def test_headline_p1_odd_length_windows(orc, sca):
-    """p = 1 for 21 MCS (with 13-MCS passes, no whole pair of them: the
-    remainder runs as passes of 11 and 10 MCS) must give the closed form; then
-    p = 1, q = 1/2 for 3 more MCS, whose windows the oracle computes from the
-    closed-form state at t = 21 (flat slopes, heights raised by 42)."""
+def run_sequence_windows(orc, lat, seq, seed, windows, w=40):
+    """Runs the (n, p, q) phases of `seq` on the lattice, then checks w x w
+    windows of heights against oracle light-cone patches that ran the same
+    phases from the flat surface."""
+    T = sum(n for n, _, _ in seq)
+    for n, p, q in seq:
+        plan = lat.plan(n, p, q)
+        _say(f"  {n} MCS p={p} q={q}: {plan['n_pass']} x {plan['kernel']}, tails {plan['tail1']}+{plan['tail2']}")
+        lat.step(n, p, q)
+    m = 2 * T + 1
+    for wx, wy in windows:
+        _say(f"  window at x={wx} y={wy} (T={T})")
+        x0, y0 = (wx - m) % lat.X, (wy - m) % lat.Y
+        patch = orc.flat_patch(lat.X, lat.Y, x0, y0, w + 2 * m, w + 2 * m)
+        for n, p, q in seq:
+            orc.run(patch, n, p, q, seed=seed)
+        got = rows_wrapped(lat, wy, w)
+        np.testing.assert_array_equal(got[:, (wx + np.arange(w)) % lat.X], patch.H[m:m + w, m:m + w])
+    assert lat.meta() == (T, int(lat.heights(0, 1)[0, 0]))
+
+
+def test_headline_draw_free_passes_from_rough_state(orc, sca):
+    """2^16 x 2^16 in the bench's launch configuration, from a rough state (4
+    MCS at p = 3/4, q = 1/4): p = 1 for 52 MCS (four 13-MCS passes on 256-row
+    bands) and 21 MCS (passes of 11 and 10), p = q = 1 for 26 MCS (the
+    general-mask form of the 13-MCS kernel), then p = 1, q = 1/2 for 3 MCS;
+    windows against oracle light-cone patches, the origin and both seams
+    among them."""
     from paper_1606_00310_amd.inputs import HEADLINE as w
 
-    _say("[fullsize] 65536^2 p=1 21 MCS, then p=1 q=0.5 3 MCS")
+    _say("[fullsize] 65536^2 rough state, then draw-free passes")
     lat = sca.Lattice(w.X, w.Y, seed=w.seed)
-    lat.step(21, 1.0, 0.0)
-    assert lat.meta() == (21, 42)
-    S = lat.slopes
-    assert bool((S[:, 0] == 0).all()) and bool((S[:, 1] == -1).all())
-    T, n = 3, 40
-    lat.step(T, 1.0, 0.5)
-    m = 2 * T + 1
-    for wx, wy in [(0, 0), (w.X - 20, w.Y - 20), (31000, 255)]:
-        _say(f"  window at x={wx} y={wy}")
-        x0, y0 = (wx - m) % w.X, (wy - m) % w.Y
-        patch = orc.flat_patch(w.X, w.Y, x0, y0, n + 2 * m, n + 2 * m)
-        patch.t, patch.h0 = 21, 42
-        patch.H += 42
-        orc.run(patch, T, 1.0, 0.5, seed=w.seed)
-        got = rows_wrapped(lat, wy, n)
-        np.testing.assert_array_equal(got[:, (wx + np.arange(n)) % w.X], patch.H[m:m + n, m:m + n])
-    assert lat.meta()[0] == 24
+    seq = [(4, 0.75, 0.25), (52, 1.0, 0.0), (21, 1.0, 0.0), (26, 1.0, 1.0), (3, 1.0, 0.5)]
+    run_sequence_windows(orc, lat, seq, w.seed, [(0, 0), (w.X - 20, w.Y - 20), (31000, 255), (12345, 40000)])
+    lat.close()
+
+
+def test_wide_draw_free_passes_from_rough_state(orc, sca):
+    """2^17 x 2^17 from a rough state: p = 1 for 12 MCS (two 6-MCS passes of
+    the 1024-thread LDS-window kernel) and 7 MCS (passes of 4 and 3), then
+    p = q = 1 for 12 MCS; windows against oracle patches."""
+    from paper_1606_00310_amd.inputs import WIDE as w
+
+    _say("[fullsize] 131072^2 rough state, then draw-free passes")
+    lat = sca.Lattice(w.X, w.Y, seed=w.seed)
+    seq = [(4, 0.75, 0.25), (12, 1.0, 0.0), (7, 1.0, 0.0), (12, 1.0, 1.0)]
+    run_sequence_windows(orc, lat, seq, w.seed, [(0, 0), (w.X - 20, 70000), (65536, w.Y - 16)])
     lat.close()
 
 
