@@ -498,8 +498,13 @@ __global__ __launch_bounds__(NW * 64) void mcs_block_lds_kernel(SweepArgs a, con
 // the update mask is T & C with T = ~A & ~B & x+ (Eq. (3) with every draw
 // accepted), and each slope it flips is x ^ (T & C): one v_bitop3 per half
 // word (truth table 0x78) instead of forming the mask and xor-ing it in.
-// edge: lane 63's next-word bit in bit 0; msb collects the top mask bit of
-// shifted rows (shifted in from the right); mp_lo, mq_lo: low mask words.
+// In shifted rows the update is applied to the aligned copy of the x+ slopes,
+// which is then shifted back by one site: bit k+1 of D takes bit k, and bit 0
+// of each lane's word takes the top bit of the previous lane's, so lane 0's
+// bit 0 is left for the exchange with the previous wave, which replaces it.
+// edge: lane 63's next-word bit in bit 0; msb collects, per half-step, the
+// new top bit of the aligned copy (the next word's bit 0, shifted in from the
+// right); mp_lo, mq_lo: low mask words.
 template <bool SH, bool HASQ>
 __device__ __forceinline__ void fixed_halfstep(uint32_t (&A)[2], uint32_t (&B)[2], uint32_t (&C)[2],
                                                uint32_t (&D)[2], uint32_t edge, uint32_t xip, uint32_t xiq,
@@ -514,41 +519,41 @@ __device__ __forceinline__ void fixed_halfstep(uint32_t (&A)[2], uint32_t (&B)[2
         XP[0] = D[0];
         XP[1] = D[1];
     }
-    uint32_t M[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         if constexpr (!HASQ) {
             const uint32_t T = __builtin_amdgcn_bitop3_b32(A[i], B[i], XP[i], 0x02);  // ~A & ~B & x+
-            M[i] = T & C[i];
+            if (i == 0) { mp_lo = T & C[0]; mq_lo = 0; }
             A[i] = __builtin_amdgcn_bitop3_b32(A[i], T, C[i], 0x78);  // A ^ (T & C)
             B[i] = __builtin_amdgcn_bitop3_b32(B[i], T, C[i], 0x78);
-            if constexpr (!SH) D[i] = __builtin_amdgcn_bitop3_b32(D[i], T, C[i], 0x78);
+            if constexpr (SH) XP[i] = __builtin_amdgcn_bitop3_b32(XP[i], T, C[i], 0x78);
+            else D[i] = __builtin_amdgcn_bitop3_b32(D[i], T, C[i], 0x78);
             C[i] = __builtin_amdgcn_bitop3_b32(C[i], T, C[i], 0x78);
-            if (i == 0) { mp_lo = M[0]; mq_lo = 0; }
         } else {
             const uint32_t mp = __builtin_amdgcn_bitop3_b32(__builtin_amdgcn_bitop3_b32(A[i], B[i], XP[i], 0x02), C[i],
                                                             xip, 0x80);  // xi & ~A & ~B & x+ & C
             const uint32_t mq = __builtin_amdgcn_bitop3_b32(__builtin_amdgcn_bitop3_b32(A[i], B[i], XP[i], 0x40), C[i],
                                                             xiq, 0x20);  // xi & A & B & ~x+ & ~C
-            M[i] = mp | mq;
-            A[i] ^= M[i];
-            B[i] ^= M[i];
-            C[i] ^= M[i];
-            if constexpr (!SH) D[i] ^= M[i];
+            const uint32_t M = mp | mq;
+            A[i] ^= M;
+            B[i] ^= M;
+            C[i] ^= M;
+            if constexpr (SH) XP[i] ^= M;
+            else D[i] ^= M;
             if (i == 0) { mp_lo = mp; mq_lo = mq; }
         }
     }
     if constexpr (SH) {
-        const uint32_t ph = from_prev_lane_or_zero(M[1]);  // bit 31: the previous word's top mask bit
-        D[0] ^= __builtin_amdgcn_alignbit(M[0], ph, 31u);
-        D[1] ^= __builtin_amdgcn_alignbit(M[1], M[0], 31u);
-        msb = __builtin_amdgcn_alignbit(msb, M[1], 31u);  // (msb << 1) | top bit
+        const uint32_t ph = from_prev_lane_or_zero(XP[1]);  // bit 31: the previous word's new top bit
+        D[0] = __builtin_amdgcn_alignbit(XP[0], ph, 31u);
+        D[1] = __builtin_amdgcn_alignbit(XP[1], XP[0], 31u);
+        msb = __builtin_amdgcn_alignbit(msb, XP[1], 31u);  // (msb << 1) | the next word's new bit 0
         asm volatile("" : "+v"(msb));
     }
-    // Pin the new slopes (and the top mask bits) here: left alone, the
-    // compiler sinks each update to where the words are read next, the next
-    // step, and keeps the masks of all 2K half-steps live until then (about
-    // 50 more VGPRs at K = 8).
+    // Pin the new slopes (and the top bits) here: left alone, the compiler
+    // sinks each update to where the words are read next, the next step, and
+    // keeps the masks of all 2K half-steps live until then (about 50 more
+    // VGPRs at K = 8).
     asm volatile("" : "+v"(A[0]), "+v"(A[1]), "+v"(B[0]), "+v"(B[1]), "+v"(C[0]), "+v"(C[1]), "+v"(D[0]), "+v"(D[1]));
 }
 
@@ -586,8 +591,8 @@ __global__ __launch_bounds__(NW * 64) void mcs_fixed_kernel(SweepArgs a, const u
         rdst[c] = __builtin_amdgcn_make_buffer_rsrc((void*)(dst + c * P), (short)0, plane_bytes, kBufferWord3);
     }
     // per wave and step: the next-word bits an aligned step passes to the
-    // wave before it, or the top mask bits a shifted step passes to the wave
-    // after it (double-buffered, one barrier per step)
+    // wave before it, or the new bit 0 of the first x+ words that a shifted
+    // step passes to the wave after it (double-buffered, one barrier per step)
     __shared__ uint32_t xs[2][NW];
     const uint32_t xip = (uint32_t)a.all_p, xiq = (uint32_t)a.all_q;
 
@@ -645,7 +650,8 @@ __global__ __launch_bounds__(NW * 64) void mcs_fixed_kernel(SweepArgs a, const u
         }
         // exchange, one barrier: an aligned step passes on the next step's
         // next-word bits (bit 0 of the x+ words of its half-steps, collected
-        // from the right), a shifted step its top mask bits
+        // from the right), a shifted step the new bit 0 of the next wave's
+        // first x+ words
         uint32_t v = 0;
         if constexpr (!SH) {
 #pragma unroll
@@ -661,11 +667,15 @@ __global__ __launch_bounds__(NW * 64) void mcs_fixed_kernel(SweepArgs a, const u
             buf ^= 1;
         }
         if constexpr (SH) {
-            // lane 0's carries: bit 0 of the x+ word of each half-step's row
+            // lane 0's bit 0 of the x+ word of each half-step's row: the new
+            // value the previous wave's lane 63 computed (its next word's bit 0)
             const uint32_t pms = (uint32_t)__builtin_amdgcn_readfirstlane((int)in);
             if (lane == 0) {
 #pragma unroll
-                for (int h = 0; h < H; ++h) Wn[sl(H - 1 - h)][1 - (h & 1)][0] ^= (pms >> (H - 1 - h)) & 1u;
+                for (int h = 0; h < H; ++h) {
+                    uint32_t& w = Wn[sl(H - 1 - h)][1 - (h & 1)][0];
+                    w = (w & ~1u) | ((pms >> (H - 1 - h)) & 1u);
+                }
             }
         } else {
             nb = in;

@@ -43,3 +43,10 @@ def test_stored_counters_name_existing_sources():
             assert e["sources"] and len(e["sources_sha256"]) == 64
             for src in e["sources"]:
                 assert os.path.exists(os.path.join(ROOT, src)), src
+
+
+def test_cpu_baseline_helpers():
+    """The oracle timing reports the threads it used and the host's CPU model."""
+    r = bench.oracle_rate(256, 256, 1.0, 0.0, 42, 64, 0.05, threads=1)
+    assert r["cores"] == 1 and r["kind"] == "oracle" and r["value"] > 0 and "1 thread" in r["sample"]
+    assert isinstance(bench.cpu_model(), str) and bench.cpu_model()

@@ -1,0 +1,129 @@
+"""Full-length parity of the workload configurations against values the
+oracle wrote (tests/golden/make_config_goldens.py calls only oracle/):
+
+* 4096 x 4096, p = 3/4, q = 1/4, seed 7: all 10^4 MCS, the exact sum h and
+  sum h^2 (and h(0,0)) at the 37 log-spaced times, the packed state's digest
+  at t = 100, 1000, 10^4 (roughening, Sec. I-A);
+* 65536 x 65536, p = 15/16, seed 42, 2000 MCS in the bench's launch
+  configuration: the 64 x 64 window of heights around the origin, across both
+  periodic seams, that an 8066-site light-cone patch gives;
+* 16384 x 16384, p = 0.93, q = 0.07 (per-site compares), seed 3: moments and
+  the two-time sums against the state at s = 100 at t = 100 .. 199 with the
+  packed digests (two-time functions, Sec. IV), and the window at T = 1000.
+"""
+import hashlib
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sca():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1606_00310_amd as P
+
+    P.lib()
+    return P
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def _sha(lat):
+    torch.cuda.synchronize()
+    return hashlib.sha256(np.ascontiguousarray(lat.slopes.cpu().numpy().view(np.uint64)).tobytes()).hexdigest()
+
+
+def _window(lat, x0, y0, w):
+    """Heights h(x, y) for x in [x0, x0+w), y in [y0, y0+w), indices mod X, Y."""
+    rows = []
+    for k in range(w):
+        y = (y0 + k) % lat.Y
+        rows.append(lat.heights(y, 1).cpu().numpy()[0])
+    h = np.stack(rows)
+    return h[:, (x0 + np.arange(w)) % lat.X].astype(np.int64)
+
+
+def test_medium_full_length(sca):
+    from paper_1606_00310_amd.inputs import MEDIUM as w
+
+    g = _golden("c2_4096x4096_p0.75_q0.25_seed7.json")
+    assert (g["X"], g["Y"], g["p"], g["q"], g["seed"]) == (w.X, w.Y, w.p, w.q, w.seed)
+    _say("[config] 4096^2 p=0.75 q=0.25, 10^4 MCS")
+    lat = sca.Lattice(w.X, w.Y, seed=w.seed)
+    t = 0
+    for row in g["moments"]:
+        lat.step(row["t"] - t, w.p, w.q)
+        t = row["t"]
+        N, s1, s2, w2 = lat.roughness()
+        assert (N, s1, s2) == (w.sites, row["sum_h"], row["sum_h2"]), t
+        assert w2 == pytest.approx(row["w2"], rel=1e-15)
+        assert lat.meta() == (t, row["h0"])
+        if str(t) in g["sha256_packed"]:
+            assert _sha(lat) == g["sha256_packed"][str(t)], t
+    assert t == w.n_mcs
+    lat.close()
+
+
+def test_headline_random_window_at_full_length(sca):
+    from paper_1606_00310_amd.inputs import HEADLINE_RANDOM as w
+
+    g = _golden("c3_65536x65536_p0.9375_seed42_window_T2000.json")
+    assert (g["X"], g["Y"], g["p"], g["q"], g["seed"], g["T"]) == (w.X, w.Y, w.p, w.q, w.seed, w.n_mcs)
+    _say("[config] 65536^2 p=0.9375, 2000 MCS, window around the origin")
+    lat = sca.Lattice(w.X, w.Y, seed=w.seed)
+    plan = lat.plan(w.n_mcs, w.p, w.q)
+    _say(f"  {plan['n_pass']} x {plan['kernel']}, tails {plan['tail1']}+{plan['tail2']}")
+    lat.step(w.n_mcs, w.p, w.q)
+    win = g["window"]
+    got = _window(lat, win["x0"], win["y0"], win["w"])
+    ref = np.array(win["heights"], np.int64)
+    np.testing.assert_array_equal(got, ref)
+    t, h0 = lat.meta()
+    assert (t, h0) == (w.n_mcs, int(ref[-win["y0"], -win["x0"]]))
+    lat.close()
+
+
+def test_persite_two_time_and_window(sca):
+    from paper_1606_00310_amd.inputs import PERSITE as w
+
+    g = _golden("c4_16384x16384_p0.93_q0.07_seed3.json")
+    assert (g["X"], g["Y"], g["p"], g["q"], g["seed"]) == (w.X, w.Y, w.p, w.q, w.seed)
+    _say("[config] 16384^2 p=0.93 q=0.07: two-time sums to t=199, window at t=1000")
+    lat = sca.Lattice(w.X, w.Y, seed=w.seed)
+    t, snap = 0, None
+    for row in g["two_time"]:
+        lat.step(row["t"] - t, w.p, w.q)
+        t = row["t"]
+        if t == row["s"]:
+            snap = lat.snapshot()
+        N, s1, s2, w2 = lat.roughness()
+        assert (N, s1, s2) == (w.sites, row["sum_h"], row["sum_h2"]), t
+        n, sts, st_, ss, c = lat.autocorr(snap)
+        assert (sts, st_, ss) == (row["sum_ht_hs"], row["sum_ht"], row["sum_hs"]), t
+        assert c == pytest.approx(row["c_ts"], rel=1e-15, abs=1e-15)
+        assert lat.meta() == (t, row["h0"])
+        assert _sha(lat) == row["sha256_packed"], t
+    win = g["window"]
+    lat.step(win["T"] - t, w.p, w.q)
+    got = _window(lat, win["x0"], win["y0"], win["w"])
+    np.testing.assert_array_equal(got, np.array(win["heights"], np.int64))
+    assert lat.meta()[1] == int(got[-win["y0"], -win["x0"]])
+    lat.close()
