@@ -185,6 +185,25 @@ def cpu_baseline(X, Y, p, q, seed, rows, budget_s):
     return out
 
 
+def comparator_rate(X, Y, p, q, seed, budget_s, max_mcs=400):
+    """The bit-vectorized CPU sweep (64-bit words, OpenMP over rows, the
+    paper's kind of CPU code, Sec. II-B) from the flat surface, one MCS at a
+    time until about budget_s seconds, on all host threads."""
+    import comparator
+
+    lat = comparator.Lattice(X, Y, seed)
+    lat.step(1, p, q)  # first touch of the state
+    n, dt = 0, 0.0
+    while dt < budget_s and n < max_mcs:
+        t0 = time.perf_counter()
+        lat.step(1, p, q)
+        dt += time.perf_counter() - t0
+        n += 1
+    return {"value": X * Y * n / dt, "unit": "site updates/s", "cores": comparator.num_threads(),
+            "kind": "bit-vectorized CPU sweep (w=64)", "cpu_model": cpu_model(),
+            "sample": f"{X}x{Y} p={p} q={q} from the flat surface, {n} MCS in {dt:.1f} s"}
+
+
 def bench_headline(torch, P, w, steps, warmup):
     """`steps` timed runs of workload w after `warmup` untimed ones.  A run
     resets the lattice to the flat surface, advances w.n_mcs MCS and takes the
@@ -360,6 +379,8 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=16384)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched ensemble and serving runs")
+    ap.add_argument("--comparator-seconds", type=float, default=8.0,
+                    help="time budget of the bit-vectorized CPU sweep (0: skip it)")
     ap.add_argument("--ensemble-only", action="store_true", help="only the batched ensemble (for profiling)")
     ap.add_argument("--only", choices=["random", "half", "persite", "wide"],
                     help="time one secondary path for --mcs MCS and print it (for profiling)")
@@ -478,6 +499,13 @@ def main():
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w.X, w.Y, w.p, w.q, w.seed, args.cpu_rows, args.cpu_seconds)
+        if args.comparator_seconds > 0:
+            # The paper's GPU/CPU comparison (Sec. III): the GPU at 2^16 x 2^16
+            # against a bit-vectorized CPU code at 2^14 x 2^14, both at p = 1/2.
+            cr = comparator_rate(16384, 16384, 0.5, 0.0, HEADLINE_HALF.seed, args.comparator_seconds)
+            gpu_half = out.get("paths", {}).get(HEADLINE_HALF.name, {}).get("value")
+            cr["gpu_p0.5_65536x65536_over_this"] = (gpu_half / cr["value"]) if gpu_half else None
+            out["cpu_comparator"] = cr
 
     print(json.dumps(out), flush=True)
 
