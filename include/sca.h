@@ -65,9 +65,11 @@ enum sca_status {
     SCA_EOVERFLOW = -4, /* an exact result does not fit its output type */
     SCA_ESTATE = -5,    /* the context failed earlier */
     SCA_EBUSY = -6,     /* a capacity limit was reached (batched calls) */
-    SCA_ENOBUF = -7     /* a temporally blocked pass was planned but no pass
+    SCA_ENOBUF = -7,    /* a temporally blocked pass was planned but no pass
                            buffer is attached (sca_set_pass_buffer); nothing
                            was changed */
+    SCA_ESCRATCH = -8   /* the lattice needs more than the static scratch of
+                           sca_roughness_noalloc (Y > SCA_NOALLOC_MAX_Y) */
 };
 
 /* sca_step_ex flags */
@@ -173,6 +175,28 @@ int sca_heights(sca_ctx* ctx, int64_t y0, int64_t ny, int32_t* out_dev);
  * roughness (Sec. I-A).  Sums are formed exactly in 128-bit arithmetic;
  * SCA_EOVERFLOW if one does not fit in int64.  Synchronizes. */
 int sca_roughness(sca_ctx* ctx, int64_t out3[3], double* w2);
+
+/* For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the exact
+ * moments of sca_roughness, out3 = {N, sum h, sum h^2} and w2, of a state
+ * given directly, with no context and no allocation of any kind.
+ *   slopes_dev: caller's device state S[2][2][Y][W] (layout above), read only
+ *   aux_dev:    caller's device int64 with h(0,0) (aux[0]), read only
+ *   X, Y:       lattice size (powers of two, 4 <= X <= 131072, 4 <= Y)
+ *   hip_stream: stream to enqueue on; it must belong to the current device
+ * The row and column sums go to a static device array of
+ * SCA_NOALLOC_SCRATCH_WORDS int64 (4 MiB + 64 B) that the library holds on
+ * each GPU it runs on until the process ends; Y > SCA_NOALLOC_MAX_Y returns
+ * SCA_ESCRATCH.  Every call on one GPU uses that GPU's single array: calls
+ * that overlap on one GPU (other host threads, other streams) race and must
+ * be serialized by the caller.  Each call writes every scratch word it reads
+ * before reading it, so nothing carries over between calls.
+ * SCA_EINVAL for invalid arguments, SCA_EOVERFLOW as sca_roughness,
+ * SCA_EDEVICE if a HIP call fails.  Synchronizes hip_stream. */
+#define SCA_NOALLOC_MAX_Y 131072
+#define SCA_NOALLOC_SCRATCH_WORDS (4 * SCA_NOALLOC_MAX_Y + 8)
+int sca_roughness_noalloc(const void* slopes_dev, const int64_t* aux_dev, int64_t X, int64_t Y,
+                          void* hip_stream, int64_t out3[3], double* w2);
 
 /* Bytes of a snapshot: the state S plus one int64 h(0,0). */
 size_t sca_snapshot_bytes(const sca_ctx* ctx);

@@ -14,6 +14,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsca.so")
 
 SCA_OK, SCA_EINVAL, SCA_ENOMEM, SCA_EDEVICE, SCA_EOVERFLOW, SCA_ESTATE, SCA_EBUSY, SCA_ENOBUF = 0, -1, -2, -3, -4, -5, -6, -7
+SCA_ESCRATCH = -8
+SCA_NOALLOC_MAX_Y = 131072
 SCA_FORCE_PERSITE = 1
 SCA_STEP_GRAPH = 2
 SCA_NO_FUSE = 4
@@ -75,6 +77,7 @@ _SIGNATURES = {
     "sca_step_ex": ([_vp, _i64, _dbl, _dbl, ctypes.c_uint], _int),
     "sca_heights": ([_vp, _i64, _i64, _vp], _int),
     "sca_roughness": ([_vp, _i64p, _dblp], _int),
+    "sca_roughness_noalloc": ([_vp, _vp, _i64, _i64, _vp, _i64p, _dblp], _int),
     "sca_snapshot_bytes": ([_vp], ctypes.c_size_t),
     "sca_snapshot": ([_vp, _vp], _int),
     "sca_autocorr": ([_vp, _vp, _i64p, _dblp], _int),

@@ -14,6 +14,7 @@
 #include <cstring>
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -274,6 +275,7 @@ const char* sca_strerror(int code)
     case SCA_ESTATE: return "context failed earlier";
     case SCA_EBUSY: return "capacity limit reached";
     case SCA_ENOBUF: return "a blocked pass needs the caller's pass buffer (sca_set_pass_buffer)";
+    case SCA_ESCRATCH: return "lattice exceeds the static scratch of the allocation-free call (Y > SCA_NOALLOC_MAX_Y)";
     default: return "unknown status";
     }
 }
@@ -468,6 +470,54 @@ int sca_roughness(sca_ctx* c, int64_t out3[3], double* w2)
     const int rc = moments_of(c->S, c->aux, c->X, c->Y, c->W, c->nb, c->ws, c->stream, out3, w2);
     if (rc == SCA_EDEVICE) return fail(c);
     return rc;
+}
+
+// Moments of a caller's state without a context and without allocation: the
+// row sums and the column prefix go to `scratch`, a static device array (one
+// copy per GPU, held until the process ends).  Host code reaches it through
+// the address hipGetSymbolAddress returns on each device, never through the
+// array's name, which on the host is only a stand-in for the symbol.
+static __device__ __align__(256) int64_t scratch[SCA_NOALLOC_SCRATCH_WORDS];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int64_t* g_scratch[kMaxDevices];  // per device: the address of `scratch`, once looked up
+
+// The address of `scratch` on the current device (looked up on the first call
+// there), or nullptr on failure.
+int64_t* scratch_on_current_device()
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_scratch[dev] = static_cast<int64_t*>(ptr);
+    }
+    return g_scratch[dev];
+}
+
+}  // namespace
+
+int sca_roughness_noalloc(const void* slopes_dev, const int64_t* aux_dev, int64_t X, int64_t Y, void* hip_stream,
+                          int64_t out3[3], double* w2)
+{
+    if (Y > SCA_NOALLOC_MAX_Y) return SCA_ESCRATCH;
+    if (!slopes_dev || !aux_dev || !out3 || !valid_size(X, Y)) return SCA_EINVAL;
+    int64_t* ws = scratch_on_current_device();
+    if (!ws) return SCA_EDEVICE;
+    // row_sums writes rows[0, 3Y) and combine writes col[0, Y) and res[0, 6)
+    // before anything reads them: nothing needs clearing between calls.
+    const int32_t W = (int32_t)(X >= 128 ? X / 128 : 1);
+    const int32_t nb = (int32_t)(X >= 128 ? 64 : X / 2);
+    return moments_of(static_cast<const uint64_t*>(slopes_dev), aux_dev, X, Y, W, nb, ws,
+                      static_cast<hipStream_t>(hip_stream), out3, w2);
 }
 
 size_t sca_snapshot_bytes(const sca_ctx* c)

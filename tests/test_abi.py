@@ -51,6 +51,14 @@ def test_host_only_calls(libsca):
     assert lib.sca_init(ctypes.byref(ctx), 100, 64, 1, 1, 1, None) == L.SCA_EINVAL
     assert lib.sca_init(ctypes.byref(ctx), 64, 64, 1, None, 1, None) == L.SCA_EINVAL
     assert lib.sca_step(None, 1, 0.5, 0.0) == L.SCA_EINVAL
+    # the allocation-free moments reject a lattice beyond their static scratch
+    # and invalid arguments before touching the device
+    out3 = (ctypes.c_int64 * 3)()
+    w2 = ctypes.c_double()
+    assert lib.sca_roughness_noalloc(1, 1, 64, 2 * L.SCA_NOALLOC_MAX_Y, None, out3, ctypes.byref(w2)) == L.SCA_ESCRATCH
+    assert lib.sca_roughness_noalloc(None, 1, 64, 64, None, out3, ctypes.byref(w2)) == L.SCA_EINVAL
+    assert lib.sca_roughness_noalloc(1, 1, 100, 64, None, out3, ctypes.byref(w2)) == L.SCA_EINVAL
+    assert lib.sca_strerror(L.SCA_ESCRATCH).decode().startswith("lattice exceeds the static scratch")
 
 
 def test_product_path_has_no_cpu_fallback():
