@@ -295,10 +295,20 @@ typedef struct sca_batch_config {
                               1024 <= X <= 8192 run as temporally blocked
                               passes of `depth` MCS (0 = never, 1 or 2): one
                               band per group of X/128 lanes, at least 8*depth
-                              rows each (groups beyond Y/(8*depth) bands idle).
+                              rows each (groups beyond Y/(8*depth) bands idle;
+                              K = 1 where even two bands of 16 rows do not fit).
                               For depth > 0 the library allocates a save area
-                              of 64*depth*block_threads bytes per persistent
-                              workgroup. */
+                              of 256*depth*block_threads bytes per persistent
+                              workgroup (and as much again per part of a split
+                              realization). */
+    int32_t max_parts;     /* 1, 2 or 4: a blocked realization whose work in
+                              the epoch exceeds the average per persistent
+                              workgroup is split into up to max_parts parts
+                              (powers of two) that run on as many workgroups at
+                              once, with one barrier among them per pass
+                              (bands of at least 8*K rows, K <= depth).  At
+                              most one part per compute unit in all, the
+                              longest realizations first. */
 } sca_batch_config;
 
 typedef struct sca_slot_info {

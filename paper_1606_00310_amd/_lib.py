@@ -40,7 +40,7 @@ class BatchConfig(ctypes.Structure):
     """sca_batch_config: launch shape and schedule of the persistent kernel."""
     _fields_ = [("block_threads", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("lds_bytes", ctypes.c_int32), ("order", ctypes.c_int32), ("words_per_lane", ctypes.c_int32),
-                ("depth", ctypes.c_int32)]
+                ("depth", ctypes.c_int32), ("max_parts", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}

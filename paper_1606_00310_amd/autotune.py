@@ -23,14 +23,14 @@ from .batch import Batch, state_bytes
 LDS_PER_CU = 160 * 1024
 
 CANDIDATES = [
-    dict(block_threads=bt, blocks_per_cu=bpc, lds_bytes=lds, order=order, words_per_lane=wpl, depth=depth)
+    dict(block_threads=bt, blocks_per_cu=bpc, lds_bytes=65536, order=0, words_per_lane=wpl, depth=depth,
+         max_parts=parts)
     for bt in (512, 1024)
-    for bpc in (1, 2, 4)
-    for lds in (0, 65536)
-    for order in (0,)
+    for bpc in (1, 2)
     for wpl in (1, 2)
-    for depth in (0, 1, 2)
-    if bpc * lds <= LDS_PER_CU and bt * bpc <= 2048
+    for depth in (1, 2)
+    for parts in (1, 2, 4)
+    if bpc * 65536 <= LDS_PER_CU and bt * bpc <= 2048
 ]
 
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_batch.json")

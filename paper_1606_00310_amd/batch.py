@@ -59,10 +59,11 @@ class Batch:
 
     # ------------------------------------------------------------ config
     def set_config(self, block_threads=None, blocks_per_cu=None, lds_bytes=None, order=None, words_per_lane=None,
-                   depth=None):
+                   depth=None, max_parts=None):
         c = self.get_config()
         for k, v in (("block_threads", block_threads), ("blocks_per_cu", blocks_per_cu), ("lds_bytes", lds_bytes),
-                     ("order", order), ("words_per_lane", words_per_lane), ("depth", depth)):
+                     ("order", order), ("words_per_lane", words_per_lane), ("depth", depth),
+                     ("max_parts", max_parts)):
             if v is not None:
                 setattr(c, k, int(v))
         L.check(L.lib().sca_batch_set_config(self._b, ctypes.byref(c)), "sca_batch_set_config")

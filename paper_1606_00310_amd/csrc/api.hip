@@ -715,7 +715,7 @@ bool valid_cfg(const sca_batch_config& c)
     return (c.block_threads == 256 || c.block_threads == 512 || c.block_threads == 1024) && c.blocks_per_cu >= 1 &&
            c.blocks_per_cu <= 8 && c.lds_bytes >= 0 && c.lds_bytes <= 65536 && (c.lds_bytes % 8) == 0 &&
            (c.order == 0 || c.order == 1) && (c.words_per_lane == 1 || c.words_per_lane == 2) && c.depth >= 0 &&
-           c.depth <= 2;
+           c.depth <= 2 && (c.max_parts == 1 || c.max_parts == 2 || c.max_parts == sca::kMaxParts);
 }
 
 }  // namespace
@@ -731,9 +731,17 @@ struct sca_batch {
     std::vector<SlotHost> slots;
     std::vector<int32_t> free_slots;  // stack of free slot ids
     ArenaAllocator alloc;
-    sca_batch_config cfg{512, 2, 65536, 0, 1, 2};
-    uint64_t* d_save = nullptr;     // save areas of the blocked passes, grid x save words
+    sca_batch_config cfg{512, 2, 65536, 0, 1, 2, 1};
+    uint64_t* d_save = nullptr;     // save areas of the blocked passes: grid x save words per workgroup,
+                                    // then grid x save words for the parts of split realizations
     size_t save_bytes = 0;
+    int64_t save_words = 0;         // per workgroup (and per part) in the captured graph
+    int32_t resident = 0;           // workgroups of the captured launch that run at once
+    int32_t* d_sync = nullptr;      // barrier counters of split realizations (one per part slot of the grid)
+    int32_t* d_err = nullptr;       // set by a barrier wait that gave up
+    int32_t* h_err = nullptr;       // pinned copy of d_err, written after each launch
+    hipEvent_t err_copied = nullptr;
+    bool err_pending = false;
     // device (library-owned)
     sca::BatchDesc* d_desc = nullptr;
     int32_t* d_order = nullptr;
@@ -762,6 +770,8 @@ int bfail(sca_batch* b)
     return SCA_EDEVICE;
 }
 
+
+
 void batch_free(sca_batch* b)
 {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -775,6 +785,10 @@ void batch_free(sca_batch* b)
     (void)hipFree(b->d_counters);
     (void)hipFree(b->d_ws);
     (void)hipFree(b->d_save);
+    (void)hipFree(b->d_sync);
+    (void)hipFree(b->d_err);
+    (void)hipHostFree(b->h_err);
+    if (b->err_copied) (void)hipEventDestroy(b->err_copied);
     (void)hipHostFree(b->h_desc);
     (void)hipHostFree(b->h_order);
     (void)hipHostFree(b->h_count);
@@ -794,8 +808,9 @@ hipError_t capture_epoch_graph(sca_batch* b)
         return hipErrorUnknown;
     const int grid = b->num_cus * b->cfg.blocks_per_cu;
     int32_t depth = b->cfg.depth;
-    int64_t save_words = 8 * (int64_t)depth * b->cfg.block_threads;
-    const size_t need = sizeof(uint64_t) * (size_t)save_words * (size_t)grid;
+    int64_t save_words = sca::blocked_save_words(depth, b->cfg.block_threads);
+    // per-workgroup save areas, then as many again for the parts of split realizations
+    const size_t need = sizeof(uint64_t) * (size_t)save_words * (size_t)grid * 2;
     if (need > b->save_bytes) {  // no launch of the old graph is in flight (callers synchronize first)
         (void)hipFree(b->d_save);
         b->d_save = nullptr;
@@ -808,10 +823,14 @@ hipError_t capture_epoch_graph(sca_batch* b)
             save_words = 0;
         }
     }
+    b->save_words = depth > 0 ? save_words : 0;
+    const int occ = sca::ensemble_occupancy(b->cfg.block_threads, b->cfg.words_per_lane, b->cfg.lds_bytes);
+    b->resident = std::min(grid, occ * b->num_cus);
     sca::BatchLaunch L{b->d_desc, b->d_order, b->d_counters, b->d_counters + 1, b->cfg.lds_bytes,
-                       depth,     b->d_save,  save_words};
+                       depth,     b->d_save,  save_words,    b->d_sync,         grid,
+                       b->d_err};
     if (hipStreamBeginCapture(b->capture, hipStreamCaptureModeRelaxed) != hipSuccess) return hipErrorUnknown;
-    hipError_t e1 = sca::launch_counter_reset(b->d_counters + 1, b->capture);
+    hipError_t e1 = sca::launch_counter_reset(b->d_counters + 1, b->d_sync, grid, b->capture);
     if (e1 == hipSuccess)
         e1 = sca::launch_ensemble(L, b->cfg.block_threads, b->cfg.words_per_lane, grid, b->capture);
     hipGraph_t graph = nullptr;
@@ -859,7 +878,11 @@ int sca_batch_create(sca_batch** out, int32_t max_slots, void* arena_dev, size_t
         delete b;
         return SCA_EDEVICE;
     }
-    const size_t nd = sizeof(sca::BatchDesc) * (size_t)max_slots, no = sizeof(int32_t) * (size_t)max_slots;
+    // the work queue holds one item per realization, plus one more per extra
+    // part of a split realization (at most one part per persistent workgroup
+    // in all, and at most 8 of those per compute unit)
+    const size_t nd = sizeof(sca::BatchDesc) * (size_t)max_slots,
+                 no = sizeof(int32_t) * ((size_t)max_slots + (size_t)b->num_cus * 8);
     if (hipMalloc(&b->d_desc, nd) != hipSuccess || hipMalloc(&b->d_order, no) != hipSuccess ||
         hipMalloc(&b->d_counters, 2 * sizeof(int32_t)) != hipSuccess ||
         hipMalloc(&b->d_ws, sizeof(int64_t) * (size_t)(4 * 131072 + 8)) != hipSuccess ||
@@ -869,12 +892,18 @@ int sca_batch_create(sca_batch** out, int32_t max_slots, void* arena_dev, size_t
         hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) != hipSuccess ||
         hipMalloc(&b->d_flat, sizeof(sca::FlatItem) * (size_t)max_slots) != hipSuccess ||
         hipHostMalloc(&b->h_flat, sizeof(sca::FlatItem) * (size_t)max_slots, hipHostMallocDefault) != hipSuccess ||
-        hipEventCreateWithFlags(&b->flat_staged, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&b->flat_staged, hipEventDisableTiming) != hipSuccess ||
+        hipMalloc(&b->d_sync, sizeof(int32_t) * (size_t)b->num_cus * 8) != hipSuccess ||
+        hipMalloc(&b->d_err, sizeof(int32_t)) != hipSuccess ||
+        hipHostMalloc(&b->h_err, sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&b->err_copied, hipEventDisableTiming) != hipSuccess ||
+        hipMemsetAsync(b->d_err, 0, sizeof(int32_t), b->stream) != hipSuccess) {
         (void)hipGetLastError();
         batch_free(b);
         return SCA_ENOMEM;
     }
     std::memset(b->h_desc, 0, nd);
+    *b->h_err = 0;
     *out = b;
     return SCA_OK;
 }
@@ -886,7 +915,10 @@ int sca_batch_set_config(sca_batch* b, const sca_batch_config* cfg)
     const bool same = cfg->block_threads == b->cfg.block_threads && cfg->blocks_per_cu == b->cfg.blocks_per_cu &&
                       cfg->lds_bytes == b->cfg.lds_bytes && cfg->order == b->cfg.order &&
                       cfg->words_per_lane == b->cfg.words_per_lane && cfg->depth == b->cfg.depth;
-    if (same) return SCA_OK;
+    if (same) {
+        b->cfg.max_parts = cfg->max_parts;  // a host-side choice: the graph stays
+        return SCA_OK;
+    }
     DeviceGuard dg(b->device);
     if (!dg.ok) return bfail(b);
     // the old graph may still be in flight on the stream
@@ -997,12 +1029,22 @@ int batch_epoch(sca_batch* b, F mcs_of, int32_t* active_out)
     if (b->failed) return SCA_ESTATE;
     DeviceGuard dg(b->device);
     if (!dg.ok) return bfail(b);
+    if (b->err_pending && hipEventQuery(b->err_copied) == hipSuccess) {
+        b->err_pending = false;
+        if (*b->h_err) return bfail(b);  // a split realization's barrier gave up: its state is not valid
+    }
     // the staging buffers are free once the previous epoch's copies have run
     if (b->staged_pending && hipEventSynchronize(b->staged) != hipSuccess) return bfail(b);
     b->staged_pending = false;
+    // The save areas and the depth of the captured graph decide which
+    // realizations can run blocked, so the graph is made first.
+    if (!b->exec && capture_epoch_graph(b) != hipSuccess) return bfail(b);
+    const int32_t grid = b->num_cus * b->cfg.blocks_per_cu;
+    const int32_t max_depth = b->save_words > 0 ? b->cfg.depth : 0;
     int32_t count = 0, hi = -1;
     std::vector<std::pair<int64_t, int32_t>> work;
     std::vector<int64_t> runs((size_t)b->max_slots, 0);
+    int64_t total = 0;
     for (int32_t slot = 0; slot < b->max_slots; ++slot) {
         SlotHost& s = b->slots[(size_t)slot];
         if (!s.used) continue;
@@ -1014,24 +1056,70 @@ int batch_epoch(sca_batch* b, F mcs_of, int32_t* active_out)
         sca::BatchDesc d = s.desc;
         d.t = (uint32_t)s.t;
         d.n_run = (uint32_t)run;
+        d.depth = 0;
+        d.bands = 0;
+        d.parts = 1;
+        d.sync_idx = 0;
+        d.save = nullptr;
+        if (d.mode == 0 && run > 0)
+            (void)sca::blocked_plan(s.W, (int)s.req.Y, max_depth, b->cfg.block_threads, 1, &d.depth, &d.bands);
         b->h_desc[slot] = d;
         hi = slot;
-        if (run > 0) work.emplace_back(run * s.req.X * s.req.Y, slot);
+        if (run > 0) {
+            work.emplace_back(run * s.req.X * s.req.Y, slot);
+            total += run * s.req.X * s.req.Y;
+        }
     }
     if (b->cfg.order == 0)
         std::stable_sort(work.begin(), work.end(),
                          [](const std::pair<int64_t, int32_t>& x, const std::pair<int64_t, int32_t>& y) {
                              return x.first > y.first;
                          });
-    // realizations that run as temporally blocked passes go first (the
-    // persistent kernel takes them in a phase of their own)
-    if (b->cfg.depth > 0)
-        std::stable_partition(work.begin(), work.end(), [b](const std::pair<int64_t, int32_t>& w) {
-            const SlotHost& s = b->slots[(size_t)w.second];
-            return s.desc.mode == 0 && sca::blocked_bands(s.W, (int)s.req.Y, b->cfg.depth, b->cfg.block_threads) > 0;
-        });
-    for (const auto& w : work) b->h_order[count++] = w.second;
-    if (active_out) *active_out = count;
+    // Realizations that run as temporally blocked passes go first (the
+    // persistent kernel takes them in a phase of their own), and among them
+    // the split ones: a blocked realization with more work than the average
+    // per persistent workgroup runs on parts = the smallest power of two that
+    // brings its share under that average (at most max_parts, as the band
+    // geometry allows), while the parts in all stay within the number of
+    // persistent workgroups that the device runs at once, so that every part
+    // is taken by a running workgroup's first pop.
+    std::stable_partition(work.begin(), work.end(), [b](const std::pair<int64_t, int32_t>& w) {
+        return b->h_desc[w.second].depth > 0;
+    });
+    const int64_t avg = total / grid;
+    int32_t parts_used = 0, n_split = 0;
+    std::vector<std::pair<int64_t, int32_t>> split, rest;
+    for (const auto& w : work) {
+        sca::BatchDesc& d = b->h_desc[w.second];
+        const SlotHost& s = b->slots[(size_t)w.second];
+        int32_t P = 1, K = d.depth, nb = d.bands;
+        if (d.depth > 0 && b->cfg.order == 0)
+            for (int32_t p2 = 2; p2 <= b->cfg.max_parts && w.first / (p2 / 2) > avg; p2 *= 2) {
+                int32_t K2 = 0, nb2 = 0;
+                if (parts_used + p2 > b->resident ||
+                    !sca::blocked_plan(s.W, (int)s.req.Y, max_depth, b->cfg.block_threads, p2, &K2, &nb2))
+                    break;
+                P = p2;
+                K = K2;
+                nb = nb2;
+            }
+        if (P > 1) {
+            d.parts = P;
+            d.depth = K;
+            d.bands = nb;
+            d.sync_idx = n_split++;
+            d.save = b->d_save + (size_t)b->save_words * (size_t)(grid + parts_used);
+            parts_used += P;
+            split.push_back(w);
+        } else {
+            rest.push_back(w);
+        }
+    }
+    for (const auto& w : split)
+        for (int32_t m = 0; m < b->h_desc[w.second].parts; ++m)
+            b->h_order[count++] = w.second | (m << sca::kItemSlotBits);
+    for (const auto& w : rest) b->h_order[count++] = w.second;
+    if (active_out) *active_out = (int32_t)work.size();
     if (count == 0) return SCA_OK;
     *b->h_count = count;
     if (hipMemcpyAsync(b->d_desc, b->h_desc, sizeof(sca::BatchDesc) * (size_t)(hi + 1), hipMemcpyHostToDevice,
@@ -1042,8 +1130,13 @@ int batch_epoch(sca_batch* b, F mcs_of, int32_t* active_out)
         hipEventRecord(b->staged, b->stream) != hipSuccess)
         return bfail(b);
     b->staged_pending = true;
-    if (!b->exec && capture_epoch_graph(b) != hipSuccess) return bfail(b);
     if (hipGraphLaunch(b->exec, b->stream) != hipSuccess) return bfail(b);
+    if (n_split > 0 && !b->err_pending) {
+        if (hipMemcpyAsync(b->h_err, b->d_err, sizeof(int32_t), hipMemcpyDeviceToHost, b->stream) != hipSuccess ||
+            hipEventRecord(b->err_copied, b->stream) != hipSuccess)
+            return bfail(b);
+        b->err_pending = true;
+    }
     for (const auto& w : work) b->slots[(size_t)w.second].t += runs[(size_t)w.second];
     return SCA_OK;
 }
@@ -1093,6 +1186,9 @@ int sca_batch_roughness(sca_batch* b, int32_t slot, int64_t out3[3], double* w2)
     const SlotHost& s = b->slots[(size_t)slot];
     const int rc = moments_of(s.desc.S, s.desc.h0, s.req.X, s.req.Y, s.W, s.nb, b->d_ws, b->stream, out3, w2);
     if (rc == SCA_EDEVICE) return bfail(b);
+    // the stream is synchronized: a barrier that gave up in an earlier launch shows in d_err
+    int32_t err = 0;
+    if (hipMemcpy(&err, b->d_err, sizeof err, hipMemcpyDeviceToHost) != hipSuccess || err) return bfail(b);
     return rc;
 }
 

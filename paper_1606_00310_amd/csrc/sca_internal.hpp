@@ -73,6 +73,18 @@ struct BatchDesc {
     uint64_t all_p, all_q;
     uint32_t t;        // MCS index at the start of the epoch
     uint32_t n_run;    // MCS to advance in this epoch (0: skip)
+    // Temporally blocked passes (phase 1 of the persistent kernel), set by
+    // the host per epoch: depth > 0 runs passes of `depth` MCS on bands of
+    // one group of W lanes each, `bands` bands per workgroup; a realization
+    // split into parts > 1 runs on as many workgroups (part m owns bands
+    // m*bands .. (m+1)*bands-1) that meet at a barrier on counter
+    // sync[sync_idx] and keep their band save slots in `save` (contiguous
+    // for all parts); parts == 1 uses the workgroup's own save area.
+    int32_t depth;
+    int32_t bands;
+    int32_t parts;
+    int32_t sync_idx;
+    uint64_t* save;
 };
 
 // Arguments of the persistent ensemble kernel; the table, the order and the
@@ -86,23 +98,61 @@ struct BatchLaunch {
     int32_t lds_bytes;       // dynamic LDS per workgroup; states up to this size run from LDS
     int32_t depth;           // MCS per blocked pass in global memory (0: none)
     uint64_t* save;          // per-workgroup save areas for the blocked passes
-    int64_t save_words;      // words per workgroup: 8 * depth * block threads
+    int64_t save_words;      // words per workgroup: 32 * depth * block threads
+    int32_t* sync;           // arrival counters of split realizations, zeroed before each launch
+    int32_t n_sync;          // number of counters
+    int32_t* err;            // set if a barrier wait of a split realization ran out of patience
 };
 
-// Bands of the temporally blocked ensemble passes of depth K over a
-// realization with dyadic p, q and rows of W = 8..64 words, for workgroups of
-// block_threads (0: it runs unblocked): one band per group of W lanes, at
-// least 8K rows each.
-__host__ __device__ inline int blocked_bands(int W, int Y, int K, int block_threads)
+// Save-area words per persistent workgroup (and per part of a split
+// realization) for blocked passes of up to `depth` MCS: each band (one group
+// of W lanes) keeps its first and its last 2K rows, two sets of each, four
+// arrays, one word per lane.
+constexpr int64_t blocked_save_words(int depth, int block_threads)
 {
-    if (K <= 0 || (W != 8 && W != 16 && W != 32 && W != 64)) return 0;
-    int nb = block_threads / W;
-    while (nb > 1 && Y / nb < 8 * K) nb >>= 1;
-    return (nb >= 2 && Y / nb >= 8 * K) ? nb : 0;
+    return 32 * (int64_t)depth * block_threads;
+}
+
+// An item of the work queue: slot in the low 20 bits, part in the bits above.
+constexpr int kItemSlotBits = 20;
+// Most parts one realization is split into.
+constexpr int kMaxParts = 4;
+
+// The blocked-pass geometry of one realization split into `parts`
+// workgroups: a depth K <= max_depth and a number of bands per workgroup (at
+// most one per group of W lanes, groups beyond it idle) that leave every
+// band at least 8K rows.  One workgroup keeps K = max_depth and idles groups
+// if it must; a split realization first lowers K to keep every group busy
+// (its parts are the ensemble's critical path).  Returns false if no K >= 1
+// works (one workgroup needs two bands).
+inline bool blocked_plan(int W, int Y, int max_depth, int block_threads, int parts, int* depth, int* bands)
+{
+    if (max_depth <= 0 || parts < 1 || (W != 8 && W != 16 && W != 32 && W != 64)) return false;
+    const int all = block_threads / W;
+    if (parts > 1)
+        for (int K = max_depth; K >= 1; --K)
+            if (Y / (all * parts) >= 8 * K && Y % (all * parts) == 0) {
+                *depth = K;
+                *bands = all;
+                return true;
+            }
+    for (int K = max_depth; K >= 1; --K) {
+        int nb = all;
+        while (nb > 1 && Y / (nb * parts) < 8 * K) nb >>= 1;
+        if (nb * parts >= 2 && Y / (nb * parts) >= 8 * K && Y % (nb * parts) == 0) {
+            *depth = K;
+            *bands = nb;
+            return true;
+        }
+    }
+    return false;
 }
 
 hipError_t launch_ensemble(const BatchLaunch& L, int block_threads, int words_per_lane, int grid, hipStream_t stream);
-hipError_t launch_counter_reset(int32_t* counter, hipStream_t stream);
+hipError_t launch_counter_reset(int32_t* counter, int32_t* sync, int32_t n_sync, hipStream_t stream);
+// Workgroups of the persistent kernel with this shape that one compute unit
+// holds at once (0 if unknown).
+int ensemble_occupancy(int block_threads, int words_per_lane, int lds_bytes);
 
 hipError_t launch_philox_rate(int64_t threads, int32_t calls, uint32_t* sink, hipStream_t stream);
 

@@ -70,11 +70,19 @@ CONFIGS = [
     dict(block_threads=512, blocks_per_cu=1, lds_bytes=16384, order=1, words_per_lane=2, depth=0),
     dict(block_threads=256, blocks_per_cu=8, lds_bytes=4096, order=0, words_per_lane=1, depth=2),
     dict(block_threads=1024, blocks_per_cu=2, lds_bytes=0, order=0, words_per_lane=1, depth=1),
+    # realizations with more work than the average per workgroup split over 2 or 4 workgroups
+    dict(block_threads=1024, blocks_per_cu=1, lds_bytes=65536, order=0, words_per_lane=2, depth=2, max_parts=4),
+    dict(block_threads=512, blocks_per_cu=2, lds_bytes=0, order=0, words_per_lane=1, depth=2, max_parts=2),
+    dict(block_threads=256, blocks_per_cu=4, lds_bytes=0, order=0, words_per_lane=1, depth=1, max_parts=4),
 ]
 
 
-@pytest.mark.parametrize("cfg", CONFIGS,
-                         ids=lambda c: "b{block_threads}-c{blocks_per_cu}-l{lds_bytes}-o{order}-w{words_per_lane}-d{depth}".format(**c))
+def _cfg_id(c):
+    return "b{block_threads}-c{blocks_per_cu}-l{lds_bytes}-o{order}-w{words_per_lane}-d{depth}".format(**c) + \
+        (f"-p{c['max_parts']}" if "max_parts" in c else "")
+
+
+@pytest.mark.parametrize("cfg", CONFIGS, ids=_cfg_id)
 @pytest.mark.parametrize("epoch", [5, 1000])
 def test_batch_equals_solo(sca, solo_states, cfg, epoch):
     from paper_1606_00310_amd.batch import Batch, state_bytes
@@ -108,6 +116,66 @@ def test_batch_matches_oracle(orc, sca):
     for r, s in zip(reals, slots):
         st = orc.flat(r.X, r.Y)
         orc.run(st, r.n_mcs, r.p, r.q, seed=r.seed, force_persite=r.force_persite)
+        S, h = b.state(s)
+        assert np.array_equal(S.cpu().numpy().view(np.uint64), orc.pack(st)), r
+        assert int(h[0]) == st.h0
+    b.close()
+
+
+# One long realization among short ones: it has more work than the average
+# per workgroup, so it runs split over 2 or 4 workgroups with barriers among
+# them (bands of 8 or 16 rows).  Rows of 8, 16 and 32 words.
+SPLIT_CASES = [
+    (2048, 2048, 0.75, 0.0, 41, 1024, 2, 4),
+    (2048, 256, 0.9375, 0.0625, 33, 256, 2, 2),
+    (1024, 1024, 0.5, 0.0, 29, 512, 2, 4),
+    (4096, 512, 1.0, 0.0, 23, 512, 1, 4),
+    (2048, 1024, 0.5, 0.5, 18, 256, 2, 4),
+]
+
+
+@pytest.mark.parametrize("X,Y,p,q,n,bt,depth,parts", SPLIT_CASES)
+def test_split_realization_equals_solo(sca, X, Y, p, q, n, bt, depth, parts):
+    from paper_1606_00310_amd.batch import Batch, Realization as R, state_bytes
+
+    _say(f"[split] {X}x{Y} p={p} q={q} n={n} block={bt} depth={depth} parts={parts}")
+    long_one = R(X, Y, p, q, n, 5150 + X // 256 + Y)
+    others = [R(64, 64, 0.5, 0.0, 3, 5200 + i) for i in range(4)] + [R(1024, 64, 0.75, 0.0, 2, 5210)]
+    reals = [long_one] + others
+    cfg = dict(block_threads=bt, blocks_per_cu=1024 // bt, lds_bytes=0, order=0, words_per_lane=1, depth=depth,
+               max_parts=parts)
+    b = Batch(max_slots=len(reals), arena_bytes=sum(state_bytes(r.X, r.Y) for r in reals), config=cfg)
+    slots = b.admit(reals)
+    for epoch in (n // 3, n):   # two epochs: the counters restart at each launch
+        b.run(epoch)
+    while b.run(n):
+        pass
+    torch.cuda.synchronize()
+    for r, s in zip(reals, slots):
+        lat = _solo(sca, r)
+        S, h = b.state(s)
+        assert torch.equal(S, lat.slopes), r
+        assert int(h[0]) == lat.meta()[1], r
+        assert b.roughness(s) == lat.roughness(), r
+        lat.close()
+    b.close()
+
+
+def test_split_realization_matches_oracle(orc, sca):
+    """A 1024 x 1024 realization split over four workgroups, from the flat
+    surface, against the oracle."""
+    from paper_1606_00310_amd.batch import Batch, Realization as R, state_bytes
+
+    reals = [R(1024, 1024, 0.75, 0.25, 11, 6101), R(64, 64, 0.5, 0.0, 2, 6102)]
+    cfg = dict(block_threads=256, blocks_per_cu=4, lds_bytes=0, order=0, words_per_lane=1, depth=2, max_parts=4)
+    b = Batch(max_slots=2, arena_bytes=sum(state_bytes(r.X, r.Y) for r in reals), config=cfg)
+    slots = b.admit(reals)
+    while b.run(11):
+        pass
+    torch.cuda.synchronize()
+    for r, s in zip(reals, slots):
+        st = orc.flat(r.X, r.Y)
+        orc.run(st, r.n_mcs, r.p, r.q, seed=r.seed)
         S, h = b.state(s)
         assert np.array_equal(S.cpu().numpy().view(np.uint64), orc.pack(st)), r
         assert int(h[0]) == st.h0
