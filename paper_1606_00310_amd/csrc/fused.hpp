@@ -78,6 +78,60 @@ __device__ __forceinline__ uint32_t from_prev_lane_or_zero(uint32_t v)
 
 __device__ __forceinline__ uint64_t join(uint32_t lo, uint32_t hi) { return (uint64_t)lo | ((uint64_t)hi << 32); }
 
+// The waves of a workgroup that share rows exchange one word per row step
+// through LDS without a barrier: four slots per wave in rotation, each word
+// carrying its exchange's tag (exchange count / 4, mod 64) above 26 value
+// bits, and each wave polls the slot of the one neighbour it needs.  A wave
+// cannot finish exchange k+1 before the reader of its exchange-k word has
+// read it (the word it waits for at k+1 is that reader's, written after the
+// reader's read at k), so a slot is never overwritten unread.
+constexpr uint32_t kExchTagShift = 26, kExchValueMask = (1u << kExchTagShift) - 1u;
+constexpr uint32_t kExchSpinLimit = 1u << 16;
+
+__device__ __forceinline__ uint32_t exch_tag(int k) { return ((uint32_t)(k >> 2) & 63u) << kExchTagShift; }
+
+// The value bits of the word tagged `tag` in *slot (an LDS word written by
+// another wave of the workgroup).  One asm block with a bounded loop (a wave
+// that is never served gives up after kExchSpinLimit reads and goes on): a
+// loop in the compiler's own code here turns the kernels' rotating register
+// windows into copies and spills.  Each read is waited for inside the block.
+__device__ __forceinline__ uint32_t exch_poll(const uint32_t* slot, uint32_t tag)
+{
+    const uint32_t addr = (uint32_t)(uintptr_t)slot;  // the LDS byte offset (low half of the flat address)
+    uint32_t w, v, t, n;
+    asm volatile(
+        "s_mov_b32 %[n], 0\n"
+        "1:\n\t"
+        "ds_read_b32 %[v], %[addr]\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_readfirstlane_b32 %[w], %[v]\n\t"
+        "s_and_b32 %[t], %[w], %[hi]\n\t"
+        "s_cmp_eq_u32 %[t], %[tag]\n\t"
+        "s_cbranch_scc1 2f\n\t"
+        "s_add_u32 %[n], %[n], 1\n\t"
+        "s_cmp_lt_u32 %[n], %[lim]\n\t"
+        "s_cbranch_scc1 1b\n"
+        "2:"
+        : [w] "=&s"(w), [v] "=&v"(v), [t] "=&s"(t), [n] "=&s"(n)
+        : [addr] "v"(addr), [tag] "s"(tag), [hi] "s"(~kExchValueMask), [lim] "s"(kExchSpinLimit)
+        : "memory", "scc");
+    return w & kExchValueMask;
+}
+
+__device__ __forceinline__ void exch_put(uint32_t* slot, uint32_t tag, uint32_t value)
+{
+    __hip_atomic_store(slot, tag | value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Fills the slots with a tag that matches none of the first four exchanges
+// (then a workgroup barrier).
+template <int NW>
+__device__ __forceinline__ void exch_init(uint32_t (&xs)[4][NW])
+{
+    if (threadIdx.x < 4 * NW) xs[threadIdx.x / NW][threadIdx.x % NW] = 63u << kExchTagShift;
+    __syncthreads();
+}
+
 // One half-step of one window row.  A, B: on-site x- and y- slopes; C: y+
 // slopes (the next row's other-sublattice y- words); D: x+ slopes (this row's
 // other-sublattice x- words).  SH: the row's x+ neighbours sit one site
@@ -147,6 +201,9 @@ __global__ __launch_bounds__(NW * 64) void mcs_block_kernel(SweepArgs a, const u
         rsrc[c] = __builtin_amdgcn_make_buffer_rsrc((void*)(src + c * P), (short)0, plane_bytes, kBufferWord3);
         rdst[c] = __builtin_amdgcn_make_buffer_rsrc((void*)(dst + c * P), (short)0, plane_bytes, kBufferWord3);
     }
+    // Exchanged once per step through LDS with a barrier (the barrier-free
+    // exchange of mcs_fixed_kernel brought nothing here: this kernel's time is
+    // in the Philox products).
     __shared__ uint32_t xa[2][NW];  // lane 0: bit 0 of the x+ words of the next step's half-steps
     __shared__ uint32_t xb[2][NW];  // lane 63: top bits of this step's masks
 
@@ -563,8 +620,9 @@ __device__ __forceinline__ void fixed_halfstep(uint32_t (&A)[2], uint32_t (&B)[2
 // DIST row steps of compute to arrive in (3; at K = 12 and 13 the window
 // alone fills the registers and a step of 2K half-steps hides a load by
 // itself).
-// Without LDS DMA the one barrier per step waits only for LDS, not for loads
-// or stores.  The first two unrolled rounds of the sweep, which hold the
+// The waves exchange their one word per step through LDS without a barrier:
+// each polls the slot of the one neighbour it needs (a workgroup barrier per
+// step cost about 9 % of the pass).  The first two unrolled rounds of the sweep, which hold the
 // band's upper halo, the origin row of band 0 and the rows not yet stored,
 // are compiled with those conditions resolved per step; the rest runs with
 // no per-half-step conditions.
@@ -590,16 +648,19 @@ __global__ __launch_bounds__(NW * 64) void mcs_fixed_kernel(SweepArgs a, const u
         rsrc[c] = __builtin_amdgcn_make_buffer_rsrc((void*)(src + c * P), (short)0, plane_bytes, kBufferWord3);
         rdst[c] = __builtin_amdgcn_make_buffer_rsrc((void*)(dst + c * P), (short)0, plane_bytes, kBufferWord3);
     }
-    // per wave and step: the next-word bits an aligned step passes to the
+    // Per wave and step: the next-word bits an aligned step passes to the
     // wave before it, or the new bit 0 of the first x+ words that a shifted
-    // step passes to the wave after it (double-buffered, one barrier per step)
-    __shared__ uint32_t xs[2][NW];
+    // step passes to the wave after it (exch_*: no barrier)
+    static_assert(H <= 26, "exchange value and tag share one word");
+    __shared__ uint32_t xs[4][NW];
+    if constexpr (NW > 1) exch_init<NW>(xs);
     const uint32_t xip = (uint32_t)a.all_p, xiq = (uint32_t)a.all_q;
 
     // [slot][array][half]; arrays 0 = x-(even), 1 = x-(odd), 2 = y-(even), 3 = y-(odd)
     uint32_t Wn[NS][4][2];
     uint32_t nb = 0;  // lane 63: the next wave's next-word bits, half-step h in bit 32-2K+h
-    int buf = 0;
+    int xk = 0;       // exchanges so far (a counter of its own: deriving it from the row index made the
+                      // compiler give up the rotating register window and spill)
 
     auto load_row = [&](uint32_t (&row)[4][2], int r) {
         const int32_t rb = (int32_t)((r & ymask) * WR * 8);
@@ -661,10 +722,14 @@ __global__ __launch_bounds__(NW * 64) void mcs_fixed_kernel(SweepArgs a, const u
                                 : (uint32_t)__builtin_amdgcn_readlane((int)v, 0);
         uint32_t in = out;  // one wave: the row wraps within it
         if constexpr (NW > 1) {
-            if (lane == 0) xs[buf][wv] = out;
-            __syncthreads();
-            in = xs[buf][SH ? (wv + NW - 1) % NW : (wv + 1) % NW];
-            buf ^= 1;
+            const uint32_t tag = exch_tag(xk);
+            uint32_t* slot = xs[xk & 3];
+            ++xk;
+            // a shifted step's word holds its 2K bits at the bottom, an aligned
+            // step's at the top (bit 32-2K+h for half-step h)
+            if (lane == 0) exch_put(&slot[wv], tag, SH ? out : (out >> (32 - H)));
+            const uint32_t w = exch_poll(&slot[SH ? (wv + NW - 1) % NW : (wv + 1) % NW], tag);
+            in = SH ? w : (w << (32 - H));
         }
         if constexpr (SH) {
             // lane 0's bit 0 of the x+ word of each half-step's row: the new
