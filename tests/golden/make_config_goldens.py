@@ -1,7 +1,7 @@
 """Writes the expected values of the full-length workload parity tests
 (tests/test_gpu_configs.py) with the CPU oracle alone.
 
-    python tests/golden/make_config_goldens.py [c2] [c3] [c4]
+    python tests/golden/make_config_goldens.py [c2] [c3] [c4] [c4s1000]
 
 Every value here comes from oracle/ (the plain one-byte-per-slope CPU
 reference); nothing is read from the GPU library.  The workloads are the
@@ -20,7 +20,8 @@ paper's benchmark shapes (Sec. III; flat start, periodic lattice):
   the whole lattice to t = 199 with the moments and the two-time sums
   against the state at s = 100 at t = 100, 125, 158, 199 (Sec. IV: two-time
   functions), and a 64 x 64 window of heights at T = 1000 around the origin
-  from a 4066-site patch.
+  from a 4066-site patch; and (c4s1000) the same at s = 1000, t = 1000 and
+  1100.
 """
 from __future__ import annotations
 
@@ -119,7 +120,31 @@ def make_c4():
         "window": {"T": T, "x0": -32, "y0": -32, "w": 64, "heights": H.tolist()}})
 
 
+def make_c4s1000():
+    """The same lattice to t = 1000 (the second waiting time of the
+    two-time functions) and t = 1100: moments, two-time sums against the
+    state at s = 1000, and the packed states' digests."""
+    w = PERSITE
+    s = 1000
+    st = oracle.flat(w.X, w.Y, track_heights=False)
+    snap = None
+    rows = []
+    t0 = time.time()
+    for T in (s, 1100):
+        oracle.run(st, T - st.t, w.p, w.q, seed=w.seed)
+        if T == s:
+            snap = st.copy()
+        N, s1, s2, w2 = oracle.moments(st)
+        _, sts, st_, ss, c = oracle.autocorr(st, snap)
+        rows.append({"t": T, "sum_h": s1, "sum_h2": s2, "w2": w2, "h0": st.h0, "s": s,
+                     "sum_ht_hs": sts, "sum_ht": st_, "sum_hs": ss, "c_ts": c, "sha256_packed": _sha(st)})
+        print(f"c4 s=1000: t={T} W2={w2:.4f} C={c:.4f} ({time.time() - t0:.0f} s)", flush=True)
+    _write("c4_16384x16384_p0.93_q0.07_seed3_s1000.json", {
+        "workload": w.name, "X": w.X, "Y": w.Y, "p": w.p, "q": w.q, "seed": w.seed,
+        "writer": "tests/golden/make_config_goldens.py (oracle only)", "two_time": rows})
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["c2", "c3", "c4"]
+    which = sys.argv[1:] or ["c2", "c3", "c4", "c4s1000"]
     for name in which:
-        {"c2": make_c2, "c3": make_c3, "c4": make_c4}[name]()
+        {"c2": make_c2, "c3": make_c3, "c4": make_c4, "c4s1000": make_c4s1000}[name]()

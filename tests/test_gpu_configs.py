@@ -9,7 +9,8 @@ oracle wrote (tests/golden/make_config_goldens.py calls only oracle/):
   periodic seams, that an 8066-site light-cone patch gives;
 * 16384 x 16384, p = 0.93, q = 0.07 (per-site compares), seed 3: moments and
   the two-time sums against the state at s = 100 at t = 100 .. 199 with the
-  packed digests (two-time functions, Sec. IV), and the window at T = 1000.
+  packed digests (two-time functions, Sec. IV), and the window at T = 1000;
+  the same at the later waiting time s = 1000 (t = 1000 and 1100).
 """
 import hashlib
 import json
@@ -126,4 +127,28 @@ def test_persite_two_time_and_window(sca):
     got = _window(lat, win["x0"], win["y0"], win["w"])
     np.testing.assert_array_equal(got, np.array(win["heights"], np.int64))
     assert lat.meta()[1] == int(got[-win["y0"], -win["x0"]])
+    lat.close()
+
+
+def test_persite_two_time_at_s1000(sca):
+    from paper_1606_00310_amd.inputs import PERSITE as w
+
+    g = _golden("c4_16384x16384_p0.93_q0.07_seed3_s1000.json")
+    assert (g["X"], g["Y"], g["p"], g["q"], g["seed"]) == (w.X, w.Y, w.p, w.q, w.seed)
+    _say("[config] 16384^2 p=0.93 q=0.07: two-time sums against s=1000 at t=1000, 1100")
+    lat = sca.Lattice(w.X, w.Y, seed=w.seed)
+    t, snap = 0, None
+    for row in g["two_time"]:
+        lat.step(row["t"] - t, w.p, w.q)
+        t = row["t"]
+        if t == row["s"]:
+            snap = lat.snapshot()
+        N, s1, s2, w2 = lat.roughness()
+        assert (N, s1, s2) == (w.sites, row["sum_h"], row["sum_h2"]), t
+        n, sts, st_, ss, c = lat.autocorr(snap)
+        assert (sts, st_, ss) == (row["sum_ht_hs"], row["sum_ht"], row["sum_hs"]), t
+        assert c == pytest.approx(row["c_ts"], rel=1e-15, abs=1e-15)
+        assert lat.meta() == (t, row["h0"])
+        assert _sha(lat) == row["sha256_packed"], t
+    assert t == 1100
     lat.close()
