@@ -25,19 +25,24 @@
  * counter (g, t, 2j+pi, 0) for call j of canonical word g = y*W + w in
  * half-step pi of MCS t.  Dyadic p, q: the 64-bit draws (lanes 0|1 then 2|3
  * of each call) folded from the last binary digit to the first, "or" for a
- * 1 digit and "and" for a 0 (Sec. III); any other p or q: site b accepts iff
- * lane b&3 of call b>>2 is below floor(r * 2^32) (Sec. II-B).
+ * 1 digit and "and" for a 0 (Sec. III); with an odd number n of draws the
+ * last one comes from the call (g, t, n-1, 0) in both half-steps of the MCS,
+ * lanes 0|1 in the even one and 2|3 in the odd one, which takes them from a
+ * per-word copy the even half-step left (p = 1/2: one call per word and
+ * MCS).  Any other p or q: site b accepts iff lane b&3 of call b>>2 is below
+ * floor(r * 2^32) (Sec. II-B).
  */
 #include <stdint.h>
 #include <string.h>
 #include <math.h>
+#include <stdlib.h>
 #ifdef _OPENMP
 #include <omp.h>
 #endif
 
 #define API __attribute__((visibility("default")))
 
-enum { BS_OK = 0, BS_EINVAL = -1 };
+enum { BS_OK = 0, BS_EINVAL = -1, BS_ENOMEM = -2 };
 
 /* Philox4x32-10: ten rounds; each round multiplies counter words 0 and 2 by
  * the published multipliers, mixes the halves with the other two words and
@@ -104,6 +109,7 @@ typedef struct {
     uint32_t k0, k1;
     accept_t P, Q;
     int persite, ndraw;
+    uint64_t* tail;     /* odd ndraw: per canonical word, lanes 2|3 of the shared last call */
 } sweep_t;
 
 /* Acceptance words of canonical word g, half-step pi, MCS t. */
@@ -125,10 +131,20 @@ static inline void accept_words(const sweep_t* s, uint32_t g, uint32_t t, int pi
         return;
     }
     uint64_t d[32];
-    for (int i = 0; i < s->ndraw; i += 2) {
+    const int pairs = s->ndraw & ~1;
+    for (int i = 0; i < pairs; i += 2) {
         philox10(g, t, (uint32_t)(i + pi), 0u, s->k0, s->k1, o);  /* call j = i/2: counter 2j + pi */
         d[i] = (uint64_t)o[0] | ((uint64_t)o[1] << 32);
         d[i + 1] = (uint64_t)o[2] | ((uint64_t)o[3] << 32);
+    }
+    if (s->ndraw & 1) {
+        if (pi == 0) {
+            philox10(g, t, (uint32_t)pairs, 0u, s->k0, s->k1, o);  /* counter n-1, both half-steps */
+            d[pairs] = (uint64_t)o[0] | ((uint64_t)o[1] << 32);
+            s->tail[g] = (uint64_t)o[2] | ((uint64_t)o[3] << 32);
+        } else {
+            d[pairs] = s->tail[g];
+        }
     }
     uint64_t ap = s->P.all ? ~(uint64_t)0 : 0, aq = s->Q.all ? ~(uint64_t)0 : 0;
     for (int i = s->ndraw; i >= 1; --i) {
@@ -213,7 +229,10 @@ API int bs_sweep(uint64_t* S, int64_t X, int64_t Y, uint64_t seed, int64_t t0, i
     s.k1 = (uint32_t)(seed >> 32);
     s.persite = !s.P.dyadic || !s.Q.dyadic;
     s.ndraw = s.P.ndig > s.Q.ndig ? s.P.ndig : s.Q.ndig;
-    if (s.ndraw & 1) s.ndraw += 1;  /* whole calls; an unused last draw is never folded */
+    if (!s.persite && (s.ndraw & 1)) {
+        s.tail = (uint64_t*)malloc((size_t)(Y * s.W) * sizeof(uint64_t));
+        if (!s.tail) return BS_ENOMEM;
+    }
     int64_t dh = 0;
     for (int64_t k = 0; k < n; ++k) {
         const uint32_t t = (uint32_t)(t0 + k);
@@ -222,6 +241,7 @@ API int bs_sweep(uint64_t* S, int64_t X, int64_t Y, uint64_t seed, int64_t t0, i
             for (int64_t y = 0; y < Y; ++y) dh += row_halfstep(&s, S, y, pi, t);
         }
     }
+    free(s.tail);
     *h0 += dh;
     return BS_OK;
 }

@@ -39,7 +39,11 @@
  *   that word yields lanes o0..o3.
  *   Dyadic r = sum_{i=1..n} b_i 2^-i (at most 32 fractional bits, Sec. III:
  *   sums of powers 1/2^i obtained with "and"/"or"): draw i-1 (i = 1..n) is
- *   o0 | o1<<32 of call (i-1)>>1 when i-1 is even, else o2 | o3<<32; the
+ *   o0 | o1<<32 of call (i-1)>>1 when i-1 is even, else o2 | o3<<32, except
+ *   that for odd n the last draw (i = n) of both half-steps of MCS t comes
+ *   from the one call with counter (g, t, n-1, 0): o0 | o1<<32 in the even
+ *   half-step, o2 | o3<<32 in the odd one (Sec. II-B: a word of xi_0.5 is
+ *   one word of random bits, so no generated bit is left unused); the
  *   acceptance word starts at 0 and for i = n down to 1 becomes
  *   (draw | acc) if b_i = 1, (draw & acc) if b_i = 0.  r = 1 accepts all,
  *   r = 0 none.  p and q share the same draws (n = max(n_p, n_q)); a site can
@@ -190,10 +194,13 @@ static void acceptance_words(uint64_t seed, uint32_t t, int parity, uint64_t g,
         uint64_t draw[32];
         for (int i = 0; i < n; ++i) {
             int j = i >> 1;
-            uint32_t ctr[4] = {(uint32_t)g, t, (uint32_t)(2 * j + parity), 0u};
+            /* the odd last draw: one call serves both half-steps of the MCS */
+            int shared = (n & 1) && i == n - 1;
+            uint32_t ctr[4] = {(uint32_t)g, t, (uint32_t)(shared ? 2 * j : 2 * j + parity), 0u};
             philox4x32_10(ctr, key, out);
-            draw[i] = (i & 1) ? ((uint64_t)out[2] | ((uint64_t)out[3] << 32))
-                              : ((uint64_t)out[0] | ((uint64_t)out[1] << 32));
+            int upper = shared ? parity : (i & 1);
+            draw[i] = upper ? ((uint64_t)out[2] | ((uint64_t)out[3] << 32))
+                            : ((uint64_t)out[0] | ((uint64_t)out[1] << 32));
         }
         *xi_p = fold_draws(P, draw);
         *xi_q = fold_draws(Q, draw);

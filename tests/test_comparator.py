@@ -37,7 +37,7 @@ def test_comparator_philox_known_answers(cmp_mod, ctr, key, expect):
 
 SIZES = [(4, 4), (8, 16), (64, 8), (128, 8), (256, 4), (512, 16)]
 PQ = [(1.0, 0.0), (0.0, 1.0), (1.0, 1.0), (0.5, 0.0), (0.75, 0.25), (0.9375, 0.0), (0.5, 0.5),
-      (0.93, 0.07), (0.3, 1.0)]
+      (0.93, 0.07), (0.3, 1.0), (0.625, 0.125)]
 
 
 @pytest.mark.parametrize("X,Y", SIZES)

@@ -72,20 +72,46 @@ def test_persite_words_follow_canonical_draws(orc, seed, t, parity):
         assert int(xp[i]) == ep and int(xq[i]) == eq
 
 
-@pytest.mark.parametrize("p,q", [(0.75, 0.25), (0.9375, 0.0), (0.5, 0.5), (1.0, 0.25)])
-def test_mask_words_follow_canonical_draws(orc, p, q):
-    seed, t, parity, g0 = 7, 31, 1, 12
+@pytest.mark.parametrize("parity", [0, 1])
+@pytest.mark.parametrize("p,q", [(0.75, 0.25), (0.9375, 0.0), (0.5, 0.5), (1.0, 0.25), (0.625, 0.0),
+                                 (0.5, 0.0), (0.34375, 0.5)])
+def test_mask_words_follow_canonical_draws(orc, p, q, parity):
+    """Draw k of word g in half-step `parity` of MCS t is lanes 0|1 (k even)
+    or 2|3 (k odd) of the call with counter (g, t, 2*(k>>1) + parity, 0); for
+    an odd number n of draws the last one (k = n-1) is taken from the call
+    (g, t, n-1, 0) in both half-steps, lanes 0|1 in the even one and 2|3 in
+    the odd one, so that each call's 128 bits are all used."""
+    seed, t, g0 = 7, 31, 12
     xp, xq = orc.acceptance_words(seed, t, parity, g0, 3, p, q)
     n = max(orc.dyadic_digits(p)[0], orc.dyadic_digits(q)[0])
     key = [seed, 0]
     for i in range(3):
         draws = []
         for k in range(n):
-            o = orc.philox4x32_10([g0 + i, t, 2 * (k >> 1) + parity, 0], key)
-            lo, hi = (o[0], o[1]) if k % 2 == 0 else (o[2], o[3])
+            if n % 2 == 1 and k == n - 1:
+                o = orc.philox4x32_10([g0 + i, t, n - 1, 0], key)
+                lo, hi = (o[0], o[1]) if parity == 0 else (o[2], o[3])
+            else:
+                o = orc.philox4x32_10([g0 + i, t, 2 * (k >> 1) + parity, 0], key)
+                lo, hi = (o[0], o[1]) if k % 2 == 0 else (o[2], o[3])
             draws.append(int(lo) | (int(hi) << 32))
         assert int(xp[i]) == orc.fold(p, draws)
         assert int(xq[i]) == orc.fold(q, draws)
+
+
+def test_half_draws_of_one_mcs_share_one_call(orc):
+    """p = 1/2 (one draw): the even and the odd half-step of an MCS take the
+    two halves of one Philox call, and no two half-steps or MCS share a word."""
+    seed, t, g0, n = 5, 9, 0, 16
+    e, _ = orc.acceptance_words(seed, t, 0, g0, n, 0.5, 0.0)
+    o, _ = orc.acceptance_words(seed, t, 1, g0, n, 0.5, 0.0)
+    e2, _ = orc.acceptance_words(seed, t + 1, 0, g0, n, 0.5, 0.0)
+    for i in range(n):
+        out = orc.philox4x32_10([g0 + i, t, 0, 0], [seed, 0])
+        assert int(e[i]) == int(out[0]) | (int(out[1]) << 32)
+        assert int(o[i]) == int(out[2]) | (int(out[3]) << 32)
+    words = [int(x) for x in list(e) + list(o) + list(e2)]
+    assert len(set(words)) == 3 * n
 
 
 def test_forced_persite_at_dyadic_r(orc):
