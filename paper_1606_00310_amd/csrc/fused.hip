@@ -58,9 +58,14 @@ void fused_kernel_name(const SweepArgs& a, XiMode mode, bool has_q, int32_t dept
         std::snprintf(out, n, "none");
         return;
     }
+    // mask passes: what the instantiation knows of the number of draws (an
+    // odd one without removals carries the shared last draw between a row's
+    // half-steps)
+    const bool rnd = mode == XiMode::Mask && !draw_free;
+    const char* odd = !rnd ? "" : ((a.ndraw & 1) == 0 ? ",Even" : (has_q ? ",Any" : ",OddTail"));
     if (a.W == 1024) {
         if (depth == kLdsDepth && draw_free) std::snprintf(out, n, "mcs_block_lds_kernel<16,%d,%s>", depth, q);
-        else std::snprintf(out, n, "mcs_block_kernel<8,2,%d,%s,%s>", depth, m, q);
+        else std::snprintf(out, n, "mcs_block_kernel<8,2,%d,%s,%s%s>", depth, m, q, odd);
         return;
     }
     const int nw = a.W / 64;
@@ -69,7 +74,7 @@ void fused_kernel_name(const SweepArgs& a, XiMode mode, bool has_q, int32_t dept
     else if (draw_free && depth >= kLdsDepth)
         std::snprintf(out, n, "mcs_block_lds_kernel<%d,%d,%s>", nw, depth, q);
     else
-        std::snprintf(out, n, "mcs_block_kernel<%d,1,%d,%s,%s>", nw, depth, m, q);
+        std::snprintf(out, n, "mcs_block_kernel<%d,1,%d,%s,%s%s>", nw, depth, m, q, odd);
 }
 
 }  // namespace sca

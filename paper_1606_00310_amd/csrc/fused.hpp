@@ -138,11 +138,11 @@ __device__ __forceinline__ void exch_init(uint32_t (&xs)[4][NW])
 // further (bit k+1, across the word edge).  nbits: lane 63's next-word bits,
 // slot i in bit i.  In shifted rows the top mask bits are or-ed into msb_acc
 // at bit `at` + i, and lane 0's incoming carry is left for the caller.
-template <bool SH, int G, int I, XiMode MODE, bool HASQ>
+template <bool SH, int G, int I, XiMode MODE, bool HASQ, Draws DR = Draws::Any>
 __device__ __forceinline__ void window_halfstep(const SweepArgs& ah, int rr, int gl, uint64_t (&A)[I],
                                                 uint64_t (&B)[I], uint64_t (&C)[I], uint64_t (&D)[I],
                                                 uint32_t nbits, uint32_t& msb_acc, int at, uint64_t& mp0,
-                                                uint64_t& mq0)
+                                                uint64_t& mq0, uint64_t* tail = nullptr)
 {
     uint64_t XP[I], M[I];
 #pragma unroll
@@ -155,7 +155,7 @@ __device__ __forceinline__ void window_halfstep(const SweepArgs& ah, int rr, int
             XP[i] = D[i];
         }
     }
-    row_masks<G, I, MODE, HASQ>(ah, rr, gl, A, B, C, XP, M, mp0, mq0);
+    row_masks<G, I, MODE, HASQ, DR>(ah, rr, gl, A, B, C, XP, M, mp0, mq0, tail);
 #pragma unroll
     for (int i = 0; i < I; ++i) {
         if constexpr (SH) {
@@ -169,7 +169,10 @@ __device__ __forceinline__ void window_halfstep(const SweepArgs& ah, int rr, int
     }
 }
 
-template <int NW, int I, int K, XiMode MODE, bool HASQ>
+// DR (mask mode): what the launch knows of the number of draws; with
+// Draws::OddTail each row's even half-step hands the shared last draw to its
+// odd one (mask_words).
+template <int NW, int I, int K, XiMode MODE, bool HASQ, Draws DR = Draws::Any>
 __global__ __launch_bounds__(NW * 64) void mcs_block_kernel(SweepArgs a, const uint64_t* src, uint64_t* dst,
                                                             int32_t band)
 {
@@ -209,6 +212,11 @@ __global__ __launch_bounds__(NW * 64) void mcs_block_kernel(SweepArgs a, const u
 
     // slot arrays: 0 = x-(even), 1 = x-(odd), 2 = y-(even), 3 = y-(odd)
     uint64_t Wn[NS][4][I];
+    // ODD: the shared last draw of a row's odd half-step, left by its even
+    // half-step one step earlier (the row keeps its slot from one step to
+    // the next, and a row that skips a half-step skips the later ones too)
+    constexpr bool TAIL = DR == Draws::OddTail && MODE == XiMode::Mask && ROT;
+    uint64_t tail[TAIL ? NS : 1][I];
     uint32_t nb0 = 0;  // lane 63: bit 0 of the next wave's first word, per (half-step, slot)
     int buf = 0;
 
@@ -269,8 +277,18 @@ __global__ __launch_bounds__(NW * 64) void mcs_block_kernel(SweepArgs a, const u
     // rotating sweep step u is shifted iff u is odd.
     auto step = [&](auto U, int s) {
         constexpr int u = decltype(U)::value;
-        if (s >= y1) return;
         auto sl = [](int j) { return (u + j) % NS; };
+        if (s >= y1) {
+            if constexpr (TAIL) {
+                // the words the next step would read, defined on this path too (it
+                // never runs: the sweep is over), so that none lives across the loop
+#pragma unroll
+                for (int h = 0; h < H; h += 2)
+#pragma unroll
+                    for (int i = 0; i < I; ++i) tail[sl(H - 1 - h)][i] = 0;
+            }
+            return;
+        }
         // Every step loads a row (the last one reloads the band's last row in
         // place of one it does not need), so that the wait before a row's
         // first use counts the same memory operations on every path.
@@ -282,7 +300,16 @@ __global__ __launch_bounds__(NW * 64) void mcs_block_kernel(SweepArgs a, const u
             const int j = H - 1 - h;          // window row of half-step h
             const int r = s + j;              // its row
             const int par = h & 1;
-            if (r < y0 - H + h) continue;     // not needed by the band's rows (and inputs not loaded)
+            if (r < y0 - H + h) {             // not needed by the band's rows (and inputs not loaded)
+                if constexpr (TAIL) {
+                    // defined on every path, so that a row's word lives only from its
+                    // even half-step to its odd one
+                    if (par == 0)
+#pragma unroll
+                        for (int i = 0; i < I; ++i) tail[sl(j)][i] = 0;
+                }
+                continue;
+            }
             const int rr = r & ymask;
             SweepArgs ah = a;
             ah.parity = par;
@@ -290,14 +317,17 @@ __global__ __launch_bounds__(NW * 64) void mcs_block_kernel(SweepArgs a, const u
             uint64_t mp0 = 0, mq0 = 0;
             const uint32_t nbits = nb0 >> (h * I);
             // row_masks indexes words as i*G + gl with G = 64*NW
+            uint64_t(&tl)[I] = tail[TAIL ? sl(j) : 0];
             if (ROT ? (u & 1) != 0 : shifted)
-                window_halfstep<true, 64 * NW, I, MODE, HASQ>(ah, rr, (int)wo, Wn[sl(j)][par], Wn[sl(j)][2 + par],
-                                                              Wn[sl(j + 1)][2 + (1 - par)], Wn[sl(j)][1 - par],
-                                                              nbits, msb_all, h * I, mp0, mq0);
+                window_halfstep<true, 64 * NW, I, MODE, HASQ, DR>(ah, rr, (int)wo, Wn[sl(j)][par],
+                                                                    Wn[sl(j)][2 + par], Wn[sl(j + 1)][2 + (1 - par)],
+                                                                    Wn[sl(j)][1 - par], nbits, msb_all, h * I, mp0,
+                                                                    mq0, tl);
             else
-                window_halfstep<false, 64 * NW, I, MODE, HASQ>(ah, rr, (int)wo, Wn[sl(j)][par], Wn[sl(j)][2 + par],
-                                                               Wn[sl(j + 1)][2 + (1 - par)], Wn[sl(j)][1 - par],
-                                                               nbits, msb_all, h * I, mp0, mq0);
+                window_halfstep<false, 64 * NW, I, MODE, HASQ, DR>(ah, rr, (int)wo, Wn[sl(j)][par],
+                                                                     Wn[sl(j)][2 + par], Wn[sl(j + 1)][2 + (1 - par)],
+                                                                     Wn[sl(j)][1 - par], nbits, msb_all, h * I, mp0,
+                                                                     mq0, tl);
             if (par == 0 && rr == 0 && r >= y0 && r < y1 && wo == 0) {
                 // one lane of the grid; an atomic needs no wait for the old value
                 const int64_t dh = 2 * (int64_t)(mp0 & 1ull) - 2 * (int64_t)(mq0 & 1ull);
@@ -801,8 +831,15 @@ hipError_t launch_block(const SweepArgs& a, XiMode mode, bool has_q, const uint6
         }
     } else if (mode == XiMode::Mask) {
         if constexpr (K <= kMaxDepthMask) {
-            if (has_q) hipLaunchKernelGGL((mcs_block_kernel<NW, I, K, XiMode::Mask, true>), grid, block, 0, stream, a, src, dst, band);
-            else hipLaunchKernelGGL((mcs_block_kernel<NW, I, K, XiMode::Mask, false>), grid, block, 0, stream, a, src, dst, band);
+            // an odd number of draws without removals (p = 1/2 among them): one
+            // Philox call per word serves both half-steps of the last draw (with
+            // removals the words kept between the half-steps would cost the
+            // 4-MCS pass its second workgroup per CU)
+            const bool odd = (a.ndraw & 1) != 0;
+            if (has_q && odd) hipLaunchKernelGGL((mcs_block_kernel<NW, I, K, XiMode::Mask, true, Draws::Any>), grid, block, 0, stream, a, src, dst, band);
+            else if (has_q) hipLaunchKernelGGL((mcs_block_kernel<NW, I, K, XiMode::Mask, true, Draws::Even>), grid, block, 0, stream, a, src, dst, band);
+            else if (odd) hipLaunchKernelGGL((mcs_block_kernel<NW, I, K, XiMode::Mask, false, Draws::OddTail>), grid, block, 0, stream, a, src, dst, band);
+            else hipLaunchKernelGGL((mcs_block_kernel<NW, I, K, XiMode::Mask, false, Draws::Even>), grid, block, 0, stream, a, src, dst, band);
         } else {
             return hipErrorInvalidValue;
         }

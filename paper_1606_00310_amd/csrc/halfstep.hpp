@@ -44,25 +44,51 @@ __device__ __forceinline__ uint64_t fold_digit(uint64_t r, uint64_t acc, uint32_
     return (uint64_t)lo | ((uint64_t)hi << 32);
 }
 
+// What a mask-mode caller knows of the number n of draws at compile time:
+// nothing (Any), that n is even (Even), or that n is odd and it keeps one
+// word per row between the row's two half-steps (OddTail).
+enum class Draws : int { Any = 0, Even = 1, OddTail = 2 };
+
 // Acceptance words for canonical word g, mask mode: the and/or fold of
 // n = ndraw draws, least significant binary digit first, generated from the
-// last Philox call backwards so that only one call's output is live.
-__device__ __forceinline__ void mask_words(const SweepArgs& a, uint32_t g, bool has_q, uint64_t& xp, uint64_t& xq)
+// last Philox call backwards so that only one call's output is live.  Call j
+// has the counter (g, t, 2j + parity, 0) and gives draws 2j and 2j+1, except
+// that for odd n the last draw of both half-steps of the MCS comes from the
+// one call (g, t, n-1, 0): lanes 0|1 in the even half-step, 2|3 in the odd
+// one.  OddTail: the even half-step leaves lanes 2|3 of that call in *tail
+// and the odd one takes its draw from there instead of calling again.
+template <Draws D = Draws::Any>
+__device__ __forceinline__ void mask_words(const SweepArgs& a, uint32_t g, bool has_q, uint64_t& xp, uint64_t& xq,
+                                           uint64_t* tail = nullptr)
 {
     uint64_t ap = 0, aq = 0;
-    const int ncall = (a.ndraw + 1) >> 1;
-    for (int j = ncall - 1; j >= 0; --j) {
-        const u32x4 o = philox4x32_10(g, a.t, 2u * (uint32_t)j + (uint32_t)a.parity, 0u, a.k0, a.k1);
-        const uint64_t r0 = (uint64_t)o.v0 | ((uint64_t)o.v1 << 32);  // draw 2j
-        const uint64_t r1 = (uint64_t)o.v2 | ((uint64_t)o.v3 << 32);  // draw 2j+1
-        const int d1 = 2 * j + 1;                                     // digit b_{2j+2}
-        if (d1 < a.ndraw) {
-            ap = fold_digit(r1, ap, (a.dig_p >> d1) & 1u);
-            if (has_q) aq = fold_digit(r1, aq, (a.dig_q >> d1) & 1u);
+    auto fold = [&](uint64_t r, int d) {  // draw d, digit b_{d+1}
+        ap = fold_digit(r, ap, (a.dig_p >> d) & 1u);
+        if (has_q) aq = fold_digit(r, aq, (a.dig_q >> d) & 1u);
+    };
+    int j = ((a.ndraw + 1) >> 1) - 1;  // the last call
+    if constexpr (D == Draws::OddTail) {
+        // n = 2j+1: the shared last draw first
+        uint64_t r;
+        if (a.parity == 1) {
+            r = *tail;
+        } else {
+            const u32x4 o = philox4x32_10(g, a.t, 2u * (uint32_t)j, 0u, a.k0, a.k1);
+            r = (uint64_t)o.v0 | ((uint64_t)o.v1 << 32);
+            *tail = (uint64_t)o.v2 | ((uint64_t)o.v3 << 32);
         }
-        const int d0 = 2 * j;                                         // digit b_{2j+1}
-        ap = fold_digit(r0, ap, (a.dig_p >> d0) & 1u);
-        if (has_q) aq = fold_digit(r0, aq, (a.dig_q >> d0) & 1u);
+        fold(r, 2 * j);
+        --j;
+    }
+    const bool odd = D == Draws::Any && (a.ndraw & 1) != 0;
+    for (; j >= 0; --j) {
+        const bool shared = odd && 2 * j + 1 == a.ndraw;  // the odd last draw: counter n-1 in both half-steps
+        const u32x4 o = philox4x32_10(g, a.t, 2u * (uint32_t)j + (shared ? 0u : (uint32_t)a.parity), 0u, a.k0, a.k1);
+        const uint64_t lo = (uint64_t)o.v0 | ((uint64_t)o.v1 << 32);
+        const uint64_t hi = (uint64_t)o.v2 | ((uint64_t)o.v3 << 32);
+        // apart from the shared draw every call gives two
+        if (D != Draws::Any || 2 * j + 1 < a.ndraw) fold(hi, 2 * j + 1);
+        fold((shared && a.parity == 1) ? hi : lo, 2 * j);
     }
     xp = ap | a.all_p;
     xq = has_q ? (aq | a.all_q) : 0;
@@ -182,17 +208,20 @@ __device__ __forceinline__ void apply_xplus(uint64_t (&D)[I], const uint64_t (&M
 // B, the y+ slopes C and the aligned x+ slopes XP, with the acceptance words
 // of sublattice a.parity at MCS a.t; A, B, C are updated in place.  mp0 and
 // mq0 return the slot-0 masks (the origin lives in bit 0 of slot 0, lane 0).
-template <int G, int I, XiMode MODE, bool HASQ>
+// D: what the caller knows of the number of draws (mask_words); with
+// Draws::OddTail, tail holds the I words that carry the shared last draw from
+// the row's even half-step to its odd one.
+template <int G, int I, XiMode MODE, bool HASQ, Draws D = Draws::Any>
 __device__ __forceinline__ void row_masks(const SweepArgs& a, int64_t y, int gl, uint64_t (&A)[I], uint64_t (&B)[I],
                                           uint64_t (&C)[I], const uint64_t (&XP)[I], uint64_t (&M)[I],
-                                          uint64_t& mp0, uint64_t& mq0)
+                                          uint64_t& mp0, uint64_t& mq0, uint64_t* tail = nullptr)
 {
 #pragma unroll
     for (int i = 0; i < I; ++i) {
         const uint32_t g = (uint32_t)(y * a.W + i * G + gl);
         uint64_t xip, xiq;
         if constexpr (MODE == XiMode::Mask) {
-            mask_words(a, g, HASQ, xip, xiq);
+            mask_words<D>(a, g, HASQ, xip, xiq, D == Draws::OddTail ? tail + i : nullptr);
         } else if constexpr (MODE == XiMode::PerSite) {
             persite_words(a, g, HASQ, xip, xiq);
         } else if constexpr (MODE == XiMode::Fixed) {

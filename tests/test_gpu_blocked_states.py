@@ -147,7 +147,11 @@ def test_reset_and_plan(orc, sca):
     assert (p20["n_pass"], p20["depth"], p20["tail1"], p20["tail2"]) == (0, 0, 10, 10)
     half = lat.plan(200, 0.5, 0.0)
     assert (half["path"], half["depth"], half["band"]) == (1, 4, 128)
-    assert half["kernel"] == "mcs_block_kernel<8,1,4,Mask,false>"
+    # one draw (odd): the instantiation that keeps the shared draw between a row's half-steps
+    assert half["kernel"] == "mcs_block_kernel<8,1,4,Mask,false,OddTail>"
+    assert lat.plan(200, 0.9375, 0.0)["kernel"] == "mcs_block_kernel<8,1,4,Mask,false,Even>"
+    assert lat.plan(200, 0.5, 0.5)["kernel"] == "mcs_block_kernel<8,1,4,Mask,true,Any>"
+    assert lat.plan(200, 0.75, 0.25)["kernel"] == "mcs_block_kernel<8,1,4,Mask,true,Even>"
     ps = lat.plan(10, 0.93, 0.07)
     assert (ps["path"], ps["n_pass"], ps["n_unfused"]) == (2, 0, 10)
     assert ps["halfstep_kernel"] == "halfstep_kernel<64,8,PerSite,true>"
