@@ -257,6 +257,28 @@ def bench_headline(torch, P, w, steps, warmup):
             "closed_form_holds": closed}
 
 
+def device_copy_rate(torch, nbytes=2**30, reps=10):
+    """HBM bytes per second (read + written) of torch's plain device copy of
+    an nbytes buffer: the mixed read/write rate this GPU delivers to a copy,
+    a practical ceiling beside the published peak."""
+    src = torch.ones(nbytes // 8, dtype=torch.int64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / sec
+
+
 def bench_ensemble(torch, P, n=4096, solo_per_L=3, tune_scale=10, serving=True, solo=True):
     """The 4096-realization ensemble in one persistent launch vs one launch
     (graph-captured MCS loop) per realization, and a serving run."""
@@ -447,6 +469,15 @@ def main():
         "paper_model_1B_per_update": {"equivalent_GBps": round(value / 1e9, 1),
                                       "note": "site updates/s x 1 B; not HBM traffic"},
     })
+    # the counted traffic of the pass against what a plain device copy of
+    # 1 GiB moves per second on this GPU (reads and writes mixed, as in the pass)
+    copy_gbs = device_copy_rate(torch) / 1e9
+    roofline["device_copy"] = {"GBps": round(copy_gbs, 1), "bytes_per_copy": 2 * 2**30,
+                               "note": "torch copy_ of 1 GiB, read + written"}
+    if roofline.get("traffic"):
+        counted = roofline["traffic"] / (avg_ms / 1e3) / 1e9
+        roofline["device_copy"].update({"pass_counted_GBps": round(counted, 1),
+                                        "pass_over_copy": round(counted / copy_gbs, 4)})
 
     out = {
         "metric": "site updates/s (bit-vectorized + arbitrary-p) vs HBM roofline; batched vs solo",

@@ -180,7 +180,7 @@ __device__ __forceinline__ void part_sync(PartSync& ps)
 // realization split over several workgroups runs the same schedule with the
 // barriers among all of its parts: this workgroup owns bands b0 ..
 // b0+nbands-1 of nbt, and `save` holds the copies of all nbt bands.
-template <int K, bool HASQ>
+template <int K, bool HASQ, Draws DR>
 __device__ __forceinline__ void blocked_passes(SweepArgs a, uint64_t* S, uint64_t* save, uint32_t t0, int npass,
                                                int nbands, int b0, int nbt, PartSync& ps)
 {
@@ -323,8 +323,8 @@ __device__ __forceinline__ void blocked_passes(SweepArgs a, uint64_t* S, uint64_
                 } else {
                     XP[0] = D[0];
                 }
-                row_masks<1, 1, XiMode::Mask, HASQ>(ah, rr, gl, Wn[sl(j)][par], Wn[sl(j)][2 + par],
-                                                     Wn[sl(j + 1)][2 + (1 - par)], XP, M, mp0, mq0);
+                row_masks<1, 1, XiMode::Mask, HASQ, DR>(ah, rr, gl, Wn[sl(j)][par], Wn[sl(j)][2 + par],
+                                                         Wn[sl(j + 1)][2 + (1 - par)], XP, M, mp0, mq0);
                 if constexpr (shifted) {
                     // D ^= M << 1 with the previous word's top mask bit at the bottom
                     const uint32_t lo = (uint32_t)M[0], hi = (uint32_t)(M[0] >> 32);
@@ -364,16 +364,29 @@ __device__ __forceinline__ void blocked_passes(SweepArgs a, uint64_t* S, uint64_
     }
 }
 
+// An even number of draws (or none) runs the passes compiled without the
+// test for the shared last draw of an odd number.
 __device__ __forceinline__ void blocked_dispatch(const SweepArgs& a, uint64_t* S, uint64_t* save, uint32_t t0,
                                                  int npass, int nbands, int b0, int nbt, int K, bool has_q,
                                                  PartSync& ps)
 {
+    const bool odd = (a.ndraw & 1) != 0;
     if (K == 1) {
-        if (has_q) blocked_passes<1, true>(a, S, save, t0, npass, nbands, b0, nbt, ps);
-        else blocked_passes<1, false>(a, S, save, t0, npass, nbands, b0, nbt, ps);
+        if (has_q) {
+            if (odd) blocked_passes<1, true, Draws::Any>(a, S, save, t0, npass, nbands, b0, nbt, ps);
+            else blocked_passes<1, true, Draws::Even>(a, S, save, t0, npass, nbands, b0, nbt, ps);
+        } else {
+            if (odd) blocked_passes<1, false, Draws::Any>(a, S, save, t0, npass, nbands, b0, nbt, ps);
+            else blocked_passes<1, false, Draws::Even>(a, S, save, t0, npass, nbands, b0, nbt, ps);
+        }
     } else {
-        if (has_q) blocked_passes<2, true>(a, S, save, t0, npass, nbands, b0, nbt, ps);
-        else blocked_passes<2, false>(a, S, save, t0, npass, nbands, b0, nbt, ps);
+        if (has_q) {
+            if (odd) blocked_passes<2, true, Draws::Any>(a, S, save, t0, npass, nbands, b0, nbt, ps);
+            else blocked_passes<2, true, Draws::Even>(a, S, save, t0, npass, nbands, b0, nbt, ps);
+        } else {
+            if (odd) blocked_passes<2, false, Draws::Any>(a, S, save, t0, npass, nbands, b0, nbt, ps);
+            else blocked_passes<2, false, Draws::Even>(a, S, save, t0, npass, nbands, b0, nbt, ps);
+        }
     }
 }
 
