@@ -293,7 +293,10 @@ typedef struct sca_batch_config {
     int32_t words_per_lane;/* word tile: 64-site words per lane in a row, 1 or 2 */
     int32_t depth;         /* realizations in global memory with dyadic p, q and
                               1024 <= X <= 8192 run as temporally blocked
-                              passes of `depth` MCS (0 = never, 1 or 2): one
+                              passes of `depth` MCS (0 = never, 1 or 2; 3 or
+                              4 only with 512-thread workgroups, one per
+                              compute unit, whose registers hold the deeper
+                              window; SCA_EINVAL otherwise): one
                               band per group of X/128 lanes, at least 8*depth
                               rows each (groups beyond Y/(8*depth) bands idle;
                               K = 1 where even two bands of 16 rows do not fit).

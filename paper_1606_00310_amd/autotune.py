@@ -22,15 +22,19 @@ from .batch import Batch, state_bytes
 
 LDS_PER_CU = 160 * 1024
 
+# Blocked passes of 2 MCS for every shape, and of 3 or 4 MCS with one
+# 512-thread workgroup per CU (the shape whose registers hold their window).
+# 1-MCS passes are left out: on MI355X they ran 1.4-1.9x slower than 2-MCS
+# passes of the same shape, since the launch streams every state from HBM.
 CANDIDATES = [
     dict(block_threads=bt, blocks_per_cu=bpc, lds_bytes=65536, order=0, words_per_lane=wpl, depth=depth,
          max_parts=parts)
     for bt in (512, 1024)
     for bpc in (1, 2)
     for wpl in (1, 2)
-    for depth in (1, 2)
+    for depth in (2, 3, 4)
     for parts in (1, 2, 4)
-    if bpc * 65536 <= LDS_PER_CU and bt * bpc <= 2048
+    if bpc * 65536 <= LDS_PER_CU and bt * bpc <= 2048 and (depth <= 2 or (bt == 512 and bpc == 1))
 ]
 
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_batch.json")

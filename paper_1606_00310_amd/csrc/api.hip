@@ -715,7 +715,8 @@ bool valid_cfg(const sca_batch_config& c)
     return (c.block_threads == 256 || c.block_threads == 512 || c.block_threads == 1024) && c.blocks_per_cu >= 1 &&
            c.blocks_per_cu <= 8 && c.lds_bytes >= 0 && c.lds_bytes <= 65536 && (c.lds_bytes % 8) == 0 &&
            (c.order == 0 || c.order == 1) && (c.words_per_lane == 1 || c.words_per_lane == 2) && c.depth >= 0 &&
-           c.depth <= 2 && (c.max_parts == 1 || c.max_parts == 2 || c.max_parts == sca::kMaxParts);
+           (c.depth <= 2 || (c.depth <= sca::kMaxBatchDepth && c.block_threads == 512 && c.blocks_per_cu == 1)) &&
+           (c.max_parts == 1 || c.max_parts == 2 || c.max_parts == sca::kMaxParts);
 }
 
 }  // namespace
@@ -824,7 +825,7 @@ hipError_t capture_epoch_graph(sca_batch* b)
         }
     }
     b->save_words = depth > 0 ? save_words : 0;
-    const int occ = sca::ensemble_occupancy(b->cfg.block_threads, b->cfg.words_per_lane, b->cfg.lds_bytes);
+    const int occ = sca::ensemble_occupancy(b->cfg.block_threads, b->cfg.words_per_lane, b->cfg.lds_bytes, depth);
     b->resident = std::min(grid, occ * b->num_cus);
     sca::BatchLaunch L{b->d_desc, b->d_order, b->d_counters, b->d_counters + 1, b->cfg.lds_bytes,
                        depth,     b->d_save,  save_words,    b->d_sync,         grid,

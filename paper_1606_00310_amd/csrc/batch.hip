@@ -364,29 +364,35 @@ __device__ __forceinline__ void blocked_passes(SweepArgs a, uint64_t* S, uint64_
     }
 }
 
-// An even number of draws (or none) runs the passes compiled without the
-// test for the shared last draw of an odd number.
+// K MCS per pass.  An even number of draws (or none) runs the passes
+// compiled without the test for the shared last draw of an odd number.
+template <int K>
+__device__ __forceinline__ void blocked_k(const SweepArgs& a, uint64_t* S, uint64_t* save, uint32_t t0, int npass,
+                                          int nbands, int b0, int nbt, bool has_q, PartSync& ps)
+{
+    const bool odd = (a.ndraw & 1) != 0;
+    if (has_q) {
+        if (odd) blocked_passes<K, true, Draws::Any>(a, S, save, t0, npass, nbands, b0, nbt, ps);
+        else blocked_passes<K, true, Draws::Even>(a, S, save, t0, npass, nbands, b0, nbt, ps);
+    } else {
+        if (odd) blocked_passes<K, false, Draws::Any>(a, S, save, t0, npass, nbands, b0, nbt, ps);
+        else blocked_passes<K, false, Draws::Even>(a, S, save, t0, npass, nbands, b0, nbt, ps);
+    }
+}
+
+// K <= MAXK MCS per pass.
+template <int MAXK>
 __device__ __forceinline__ void blocked_dispatch(const SweepArgs& a, uint64_t* S, uint64_t* save, uint32_t t0,
                                                  int npass, int nbands, int b0, int nbt, int K, bool has_q,
                                                  PartSync& ps)
 {
-    const bool odd = (a.ndraw & 1) != 0;
     if (K == 1) {
-        if (has_q) {
-            if (odd) blocked_passes<1, true, Draws::Any>(a, S, save, t0, npass, nbands, b0, nbt, ps);
-            else blocked_passes<1, true, Draws::Even>(a, S, save, t0, npass, nbands, b0, nbt, ps);
-        } else {
-            if (odd) blocked_passes<1, false, Draws::Any>(a, S, save, t0, npass, nbands, b0, nbt, ps);
-            else blocked_passes<1, false, Draws::Even>(a, S, save, t0, npass, nbands, b0, nbt, ps);
-        }
-    } else {
-        if (has_q) {
-            if (odd) blocked_passes<2, true, Draws::Any>(a, S, save, t0, npass, nbands, b0, nbt, ps);
-            else blocked_passes<2, true, Draws::Even>(a, S, save, t0, npass, nbands, b0, nbt, ps);
-        } else {
-            if (odd) blocked_passes<2, false, Draws::Any>(a, S, save, t0, npass, nbands, b0, nbt, ps);
-            else blocked_passes<2, false, Draws::Even>(a, S, save, t0, npass, nbands, b0, nbt, ps);
-        }
+        blocked_k<1>(a, S, save, t0, npass, nbands, b0, nbt, has_q, ps);
+    } else if (MAXK < 3 || K == 2) {
+        blocked_k<2>(a, S, save, t0, npass, nbands, b0, nbt, has_q, ps);
+    } else if constexpr (MAXK >= 4) {
+        if (K == 3) blocked_k<3>(a, S, save, t0, npass, nbands, b0, nbt, has_q, ps);
+        else blocked_k<4>(a, S, save, t0, npass, nbands, b0, nbt, has_q, ps);
     }
 }
 
@@ -438,7 +444,10 @@ __device__ __forceinline__ int32_t next_item(int32_t* queue, int32_t* s_item)
     return __builtin_amdgcn_readfirstlane(*s_item);
 }
 
-template <int BLOCK, int IW>
+// MAXK: the deepest blocked pass compiled in (its register window decides
+// how many workgroups a CU holds: 2 fits 1024-thread workgroups, 4 one
+// 512-thread workgroup per CU).
+template <int BLOCK, int IW, int MAXK>
 __global__ __launch_bounds__(BLOCK) void ensemble_kernel(BatchLaunch L)
 {
     constexpr int NWAVES = BLOCK / 64;
@@ -465,10 +474,11 @@ __global__ __launch_bounds__(BLOCK) void ensemble_kernel(BatchLaunch L)
             PartSync ps{d.parts > 1 ? L.sync + d.sync_idx : nullptr, d.parts, 0, L.err, false};
             const int nbt = d.bands * d.parts, b0 = part * d.bands;
             const int npass = (int)(d.n_run / (uint32_t)d.depth);
-            if (npass > 0) blocked_dispatch(a, d.S, save, d.t, npass, d.bands, b0, nbt, d.depth, has_q, ps);
+            if (npass > 0) blocked_dispatch<MAXK>(a, d.S, save, d.t, npass, d.bands, b0, nbt, d.depth, has_q, ps);
             const uint32_t done = (uint32_t)npass * (uint32_t)d.depth;
             if (done < d.n_run)
-                blocked_dispatch(a, d.S, save, d.t + done, (int)(d.n_run - done), d.bands, b0, nbt, 1, has_q, ps);
+                blocked_dispatch<MAXK>(a, d.S, save, d.t + done, (int)(d.n_run - done), d.bands, b0, nbt, 1, has_q,
+                                       ps);
         }
         item = next_item(L.queue, &s_item);
     }
@@ -517,38 +527,46 @@ __global__ void counter_reset_kernel(int32_t* c, int32_t* sync, int32_t n_sync)
     if (i < n_sync) sync[i] = 0;
 }
 
+// The kernel instantiation of a configuration: passes of up to 2 MCS for
+// every shape, of up to 4 MCS for one 512-thread workgroup per CU.
+template <class F>
+hipError_t with_ensemble_kernel(int block_threads, int words_per_lane, int depth, F&& f)
+{
+    if (depth > 2) {
+        if (block_threads != 512) return hipErrorInvalidValue;
+        if (words_per_lane == 1) return f(ensemble_kernel<512, 1, 4>);
+        if (words_per_lane == 2) return f(ensemble_kernel<512, 2, 4>);
+        return hipErrorInvalidValue;
+    }
+    switch (block_threads * 4 + words_per_lane) {
+    case 256 * 4 + 1: return f(ensemble_kernel<256, 1, 2>);
+    case 512 * 4 + 1: return f(ensemble_kernel<512, 1, 2>);
+    case 1024 * 4 + 1: return f(ensemble_kernel<1024, 1, 2>);
+    case 256 * 4 + 2: return f(ensemble_kernel<256, 2, 2>);
+    case 512 * 4 + 2: return f(ensemble_kernel<512, 2, 2>);
+    case 1024 * 4 + 2: return f(ensemble_kernel<1024, 2, 2>);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_ensemble(const BatchLaunch& L, int block_threads, int words_per_lane, int grid, hipStream_t stream)
 {
     const size_t lds = (size_t)L.lds_bytes;
-    const int key = block_threads * 4 + words_per_lane;
-    switch (key) {
-    case 256 * 4 + 1: hipLaunchKernelGGL((ensemble_kernel<256, 1>), dim3(grid), dim3(256), lds, stream, L); break;
-    case 512 * 4 + 1: hipLaunchKernelGGL((ensemble_kernel<512, 1>), dim3(grid), dim3(512), lds, stream, L); break;
-    case 1024 * 4 + 1: hipLaunchKernelGGL((ensemble_kernel<1024, 1>), dim3(grid), dim3(1024), lds, stream, L); break;
-    case 256 * 4 + 2: hipLaunchKernelGGL((ensemble_kernel<256, 2>), dim3(grid), dim3(256), lds, stream, L); break;
-    case 512 * 4 + 2: hipLaunchKernelGGL((ensemble_kernel<512, 2>), dim3(grid), dim3(512), lds, stream, L); break;
-    case 1024 * 4 + 2: hipLaunchKernelGGL((ensemble_kernel<1024, 2>), dim3(grid), dim3(1024), lds, stream, L); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    return with_ensemble_kernel(block_threads, words_per_lane, L.depth, [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(block_threads), lds, stream, L);
+        return hipGetLastError();
+    });
 }
 
-int ensemble_occupancy(int block_threads, int words_per_lane, int lds_bytes)
+int ensemble_occupancy(int block_threads, int words_per_lane, int lds_bytes, int depth)
 {
     int n = 0;
     const size_t lds = (size_t)lds_bytes;
-    hipError_t e = hipErrorInvalidValue;
-    switch (block_threads * 4 + words_per_lane) {
-    case 256 * 4 + 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ensemble_kernel<256, 1>, 256, lds); break;
-    case 512 * 4 + 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ensemble_kernel<512, 1>, 512, lds); break;
-    case 1024 * 4 + 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ensemble_kernel<1024, 1>, 1024, lds); break;
-    case 256 * 4 + 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ensemble_kernel<256, 2>, 256, lds); break;
-    case 512 * 4 + 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ensemble_kernel<512, 2>, 512, lds); break;
-    case 1024 * 4 + 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ensemble_kernel<1024, 2>, 1024, lds); break;
-    default: break;
-    }
+    const hipError_t e = with_ensemble_kernel(block_threads, words_per_lane, depth, [&](auto kernel) {
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, block_threads, lds);
+    });
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return 0;

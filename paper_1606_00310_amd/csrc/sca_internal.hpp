@@ -117,6 +117,9 @@ constexpr int64_t blocked_save_words(int depth, int block_threads)
 constexpr int kItemSlotBits = 20;
 // Most parts one realization is split into.
 constexpr int kMaxParts = 4;
+// Deepest blocked pass of the persistent kernel (one 512-thread workgroup per
+// CU; other shapes go to 2 MCS).
+constexpr int kMaxBatchDepth = 4;
 
 // The blocked-pass geometry of one realization split into `parts`
 // workgroups: a depth K <= max_depth and a number of bands per workgroup (at
@@ -152,7 +155,7 @@ hipError_t launch_ensemble(const BatchLaunch& L, int block_threads, int words_pe
 hipError_t launch_counter_reset(int32_t* counter, int32_t* sync, int32_t n_sync, hipStream_t stream);
 // Workgroups of the persistent kernel with this shape that one compute unit
 // holds at once (0 if unknown).
-int ensemble_occupancy(int block_threads, int words_per_lane, int lds_bytes);
+int ensemble_occupancy(int block_threads, int words_per_lane, int lds_bytes, int depth);
 
 hipError_t launch_philox_rate(int64_t threads, int32_t calls, uint32_t* sink, hipStream_t stream);
 

@@ -74,6 +74,10 @@ CONFIGS = [
     dict(block_threads=1024, blocks_per_cu=1, lds_bytes=65536, order=0, words_per_lane=2, depth=2, max_parts=4),
     dict(block_threads=512, blocks_per_cu=2, lds_bytes=0, order=0, words_per_lane=1, depth=2, max_parts=2),
     dict(block_threads=256, blocks_per_cu=4, lds_bytes=0, order=0, words_per_lane=1, depth=1, max_parts=4),
+    # 3- and 4-MCS passes: one 512-thread workgroup per CU
+    dict(block_threads=512, blocks_per_cu=1, lds_bytes=65536, order=0, words_per_lane=1, depth=4),
+    dict(block_threads=512, blocks_per_cu=1, lds_bytes=0, order=0, words_per_lane=2, depth=3, max_parts=4),
+    dict(block_threads=512, blocks_per_cu=1, lds_bytes=0, order=1, words_per_lane=1, depth=4, max_parts=2),
 ]
 
 
@@ -131,6 +135,8 @@ SPLIT_CASES = [
     (1024, 1024, 0.5, 0.0, 29, 512, 2, 4),
     (4096, 512, 1.0, 0.0, 23, 512, 1, 4),
     (2048, 1024, 0.5, 0.5, 18, 256, 2, 4),
+    (2048, 2048, 0.5, 0.0, 37, 512, 4, 2),
+    (4096, 1024, 0.9375, 0.0625, 21, 512, 3, 4),
 ]
 
 
@@ -142,8 +148,8 @@ def test_split_realization_equals_solo(sca, X, Y, p, q, n, bt, depth, parts):
     long_one = R(X, Y, p, q, n, 5150 + X // 256 + Y)
     others = [R(64, 64, 0.5, 0.0, 3, 5200 + i) for i in range(4)] + [R(1024, 64, 0.75, 0.0, 2, 5210)]
     reals = [long_one] + others
-    cfg = dict(block_threads=bt, blocks_per_cu=1024 // bt, lds_bytes=0, order=0, words_per_lane=1, depth=depth,
-               max_parts=parts)
+    cfg = dict(block_threads=bt, blocks_per_cu=1 if depth > 2 else 1024 // bt, lds_bytes=0, order=0,
+               words_per_lane=1, depth=depth, max_parts=parts)
     b = Batch(max_slots=len(reals), arena_bytes=sum(state_bytes(r.X, r.Y) for r in reals), config=cfg)
     slots = b.admit(reals)
     for epoch in (n // 3, n):   # two epochs: the counters restart at each launch
@@ -180,6 +186,42 @@ def test_split_realization_matches_oracle(orc, sca):
         assert np.array_equal(S.cpu().numpy().view(np.uint64), orc.pack(st)), r
         assert int(h[0]) == st.h0
     b.close()
+
+
+@pytest.mark.parametrize("depth,parts", [(4, 1), (3, 2), (4, 4)])
+def test_deep_batch_passes_match_oracle(orc, sca, depth, parts):
+    """3- and 4-MCS blocked passes of the persistent kernel (one 512-thread
+    workgroup per CU), whole and split, from the flat surface, against the
+    oracle: 16- and 8-word rows, q > 0 and an odd number of draws."""
+    from paper_1606_00310_amd.batch import Batch, Realization as R, state_bytes
+
+    reals = [R(2048, 512, 0.75, 0.25, 13, 6201), R(1024, 1024, 0.5, 0.0, 10, 6202), R(64, 64, 0.5, 0.0, 2, 6203)]
+    cfg = dict(block_threads=512, blocks_per_cu=1, lds_bytes=0, order=0, words_per_lane=1, depth=depth,
+               max_parts=parts)
+    _say(f"[batch] deep passes depth={depth} parts={parts}")
+    b = Batch(max_slots=len(reals), arena_bytes=sum(state_bytes(r.X, r.Y) for r in reals), config=cfg)
+    slots = b.admit(reals)
+    while b.run(13):
+        pass
+    torch.cuda.synchronize()
+    for r, s in zip(reals, slots):
+        st = orc.flat(r.X, r.Y)
+        orc.run(st, r.n_mcs, r.p, r.q, seed=r.seed)
+        S, h = b.state(s)
+        assert np.array_equal(S.cpu().numpy().view(np.uint64), orc.pack(st)), r
+        assert int(h[0]) == st.h0
+    b.close()
+
+
+def test_deep_batch_passes_need_one_512_thread_workgroup_per_cu(sca):
+    from paper_1606_00310_amd import ScaError
+    from paper_1606_00310_amd.batch import Batch, state_bytes
+
+    for cfg in (dict(block_threads=1024, blocks_per_cu=1, depth=3), dict(block_threads=512, blocks_per_cu=2, depth=4),
+                dict(block_threads=512, blocks_per_cu=1, depth=5)):
+        full = dict(lds_bytes=0, order=0, words_per_lane=1, max_parts=1, **cfg)
+        with pytest.raises(ScaError):
+            Batch(max_slots=1, arena_bytes=state_bytes(64, 64), config=full)
 
 
 def test_admission_budget_and_reuse(sca):
