@@ -256,6 +256,9 @@ __device__ __forceinline__ void blocked_passes(SweepArgs a, uint64_t* S, uint64_
         a.t = t0 + (uint32_t)(pass * K);
         const int rd = pass & 1, wr = rd ^ 1;
         uint64_t Wn[NS][4][1];
+        // OddTail: a row's shared last draw, from its even half-step to its odd one
+        constexpr bool TAIL = DR == Draws::OddTail;
+        uint64_t tail[TAIL ? NS : 1][1];
         // Rows are addressed relative to the band start y0: the same for every
         // group at a given step, so the branches below are uniform and each
         // load keeps one buffer descriptor.  Rows above y0-2K feed no
@@ -291,8 +294,16 @@ __device__ __forceinline__ void blocked_passes(SweepArgs a, uint64_t* S, uint64_
         // time in the unrolled steps.
         auto step = [&](auto U, int k) {
             constexpr int u = decltype(U)::value;
-            if (k >= nsteps) return;
             auto sl = [](int j) { return (u + j) % NS; };
+            if (k >= nsteps) {
+                if constexpr (TAIL) {
+                    // defined on this path too (it never runs on: the sweep is over), so
+                    // that no kept word lives across the loop
+#pragma unroll
+                    for (int h = 0; h < H; h += 2) tail[sl(H - 1 - h)][0] = 0;
+                }
+                return;
+            }
             constexpr bool shifted = (u & 1) != 0;
             const int q = k - 2 * H + 1;      // this step's first window row, relative to y0
             // every step loads a row (the last ones reload the last row of the
@@ -304,7 +315,12 @@ __device__ __forceinline__ void blocked_passes(SweepArgs a, uint64_t* S, uint64_
                 const int j = H - 1 - h;
                 const int rel = q + j;
                 const int par = h & 1;
-                if (rel < -H + h) continue;
+                if (rel < -H + h) {
+                    if constexpr (TAIL) {
+                        if (par == 0) tail[sl(j)][0] = 0;  // defined on every path
+                    }
+                    continue;
+                }
                 const int rr = (y0 + rel) & ymask;
                 SweepArgs ah = a;
                 ah.parity = par;
@@ -324,7 +340,8 @@ __device__ __forceinline__ void blocked_passes(SweepArgs a, uint64_t* S, uint64_
                     XP[0] = D[0];
                 }
                 row_masks<1, 1, XiMode::Mask, HASQ, DR>(ah, rr, gl, Wn[sl(j)][par], Wn[sl(j)][2 + par],
-                                                         Wn[sl(j + 1)][2 + (1 - par)], XP, M, mp0, mq0);
+                                                         Wn[sl(j + 1)][2 + (1 - par)], XP, M, mp0, mq0,
+                                                         tail[TAIL ? sl(j) : 0]);
                 if constexpr (shifted) {
                     // D ^= M << 1 with the previous word's top mask bit at the bottom
                     const uint32_t lo = (uint32_t)M[0], hi = (uint32_t)(M[0] >> 32);
@@ -365,8 +382,11 @@ __device__ __forceinline__ void blocked_passes(SweepArgs a, uint64_t* S, uint64_
 }
 
 // K MCS per pass.  An even number of draws (or none) runs the passes
-// compiled without the test for the shared last draw of an odd number.
-template <int K>
+// compiled without the test for the shared last draw of an odd number; with
+// TAIL (a kernel shape with registers to spare) an odd number without
+// removals keeps that draw between a row's two half-steps (one Philox call
+// per word and MCS for p = 1/2).
+template <int K, bool TAIL>
 __device__ __forceinline__ void blocked_k(const SweepArgs& a, uint64_t* S, uint64_t* save, uint32_t t0, int npass,
                                           int nbands, int b0, int nbt, bool has_q, PartSync& ps)
 {
@@ -375,7 +395,8 @@ __device__ __forceinline__ void blocked_k(const SweepArgs& a, uint64_t* S, uint6
         if (odd) blocked_passes<K, true, Draws::Any>(a, S, save, t0, npass, nbands, b0, nbt, ps);
         else blocked_passes<K, true, Draws::Even>(a, S, save, t0, npass, nbands, b0, nbt, ps);
     } else {
-        if (odd) blocked_passes<K, false, Draws::Any>(a, S, save, t0, npass, nbands, b0, nbt, ps);
+        if (odd) blocked_passes<K, false, TAIL ? Draws::OddTail : Draws::Any>(a, S, save, t0, npass, nbands, b0, nbt,
+                                                                              ps);
         else blocked_passes<K, false, Draws::Even>(a, S, save, t0, npass, nbands, b0, nbt, ps);
     }
 }
@@ -386,13 +407,14 @@ __device__ __forceinline__ void blocked_dispatch(const SweepArgs& a, uint64_t* S
                                                  int npass, int nbands, int b0, int nbt, int K, bool has_q,
                                                  PartSync& ps)
 {
+    constexpr bool TAIL = MAXK >= 4;  // the 512-thread, one-per-CU shape
     if (K == 1) {
-        blocked_k<1>(a, S, save, t0, npass, nbands, b0, nbt, has_q, ps);
+        blocked_k<1, TAIL>(a, S, save, t0, npass, nbands, b0, nbt, has_q, ps);
     } else if (MAXK < 3 || K == 2) {
-        blocked_k<2>(a, S, save, t0, npass, nbands, b0, nbt, has_q, ps);
+        blocked_k<2, TAIL>(a, S, save, t0, npass, nbands, b0, nbt, has_q, ps);
     } else if constexpr (MAXK >= 4) {
-        if (K == 3) blocked_k<3>(a, S, save, t0, npass, nbands, b0, nbt, has_q, ps);
-        else blocked_k<4>(a, S, save, t0, npass, nbands, b0, nbt, has_q, ps);
+        if (K == 3) blocked_k<3, TAIL>(a, S, save, t0, npass, nbands, b0, nbt, has_q, ps);
+        else blocked_k<4, TAIL>(a, S, save, t0, npass, nbands, b0, nbt, has_q, ps);
     }
 }
 
