@@ -26,7 +26,10 @@
  * g = y*W + w is the canonical word, t the 0-based MCS index and j the call
  * index within the word.  Dyadic p and q (p*2^32 and q*2^32 integers;
  * Sec. III: sums of powers 1/2^i via and/or) fold n = max(n_p, n_q) 64-bit
- * draws, least significant binary digit first; any other p or q compares one
+ * draws (lanes 0|1, then 2|3 of each call), least significant binary digit
+ * first; for odd n the last draw of both half-steps of an MCS comes from the
+ * one call (g, t, n-1, 0), lanes 0|1 in the even half-step and 2|3 in the
+ * odd one (p = 1/2: one call per word and MCS); any other p or q compares one
  * 32-bit uniform per site with floor(r * 2^32) (Sec. II-B), 16 calls per word.
  *
  * Conventions for every call:

@@ -1,7 +1,9 @@
 """The oracle's MCS loop draws the acceptance words of the even half-step of
 MCS t from the counter (g, t, 2j+0, 0) and then those of the odd half-step
-from (g, t, 2j+1, 0) (Sec. I-A: one MCS is the even, then the odd half-step;
-the counter layout is the documented convention of the random stream).  One
+from (g, t, 2j+1, 0), except for the shared last draw of an odd number n of
+draws, which both half-steps take from (g, t, n-1, 0) (Sec. I-A: one MCS is
+the even, then the odd half-step; the counter layout is the documented
+convention of the random stream).  One
 MCS of ``run`` from an absolute time t0 != 0 must therefore equal two
 half-steps with the words ``acceptance_words(seed, t0, 0)`` and
 ``acceptance_words(seed, t0, 1)`` injected, in that order.  A counter off by
@@ -27,7 +29,7 @@ def _injected_mcs(orc, st, seed, p, q, persite):
 
 
 @pytest.mark.parametrize("p,q,persite", [(0.75, 0.25, False), (0.9375, 0.0, False), (0.93, 0.07, False),
-                                         (0.5, 0.5, True)])
+                                         (0.5, 0.5, True), (0.5, 0.0, False), (0.625, 0.125, False)])
 @pytest.mark.parametrize("X,Y,t0", [(256, 16, 37), (64, 32, 1), (512, 8, 4000000000)])
 def test_one_mcs_equals_two_injected_halfsteps(orc, p, q, persite, X, Y, t0):
     seed = 0x1234_5678_9ABC_DEF1
