@@ -297,8 +297,8 @@ __device__ __forceinline__ void blocked_passes(SweepArgs a, uint64_t* S, uint64_
             auto sl = [](int j) { return (u + j) % NS; };
             if (k >= nsteps) {
                 if constexpr (TAIL) {
-                    // defined on this path too (it never runs on: the sweep is over), so
-                    // that no kept word lives across the loop
+                    // defined on this path too (no step runs after it: the sweep is
+                    // over), so that no kept word lives across the loop
 #pragma unroll
                     for (int h = 0; h < H; h += 2) tail[sl(H - 1 - h)][0] = 0;
                 }

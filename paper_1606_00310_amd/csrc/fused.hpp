@@ -212,7 +212,7 @@ __global__ __launch_bounds__(NW * 64) void mcs_block_kernel(SweepArgs a, const u
 
     // slot arrays: 0 = x-(even), 1 = x-(odd), 2 = y-(even), 3 = y-(odd)
     uint64_t Wn[NS][4][I];
-    // ODD: the shared last draw of a row's odd half-step, left by its even
+    // TAIL: the shared last draw of a row's odd half-step, left by its even
     // half-step one step earlier (the row keeps its slot from one step to
     // the next, and a row that skips a half-step skips the later ones too)
     constexpr bool TAIL = DR == Draws::OddTail && MODE == XiMode::Mask && ROT;
@@ -280,8 +280,9 @@ __global__ __launch_bounds__(NW * 64) void mcs_block_kernel(SweepArgs a, const u
         auto sl = [](int j) { return (u + j) % NS; };
         if (s >= y1) {
             if constexpr (TAIL) {
-                // the words the next step would read, defined on this path too (it
-                // never runs: the sweep is over), so that none lives across the loop
+                // the words the next step would read, defined on this path too (no
+                // step runs after it: the sweep is over), so that none of them lives
+                // across the loop
 #pragma unroll
                 for (int h = 0; h < H; h += 2)
 #pragma unroll
