@@ -258,25 +258,30 @@ def bench_headline(torch, P, w, steps, warmup):
 
 
 def device_copy_rate(torch, nbytes=2**30, reps=10):
-    """HBM bytes per second (read + written) of torch's plain device copy of
-    an nbytes buffer: the mixed read/write rate this GPU delivers to a copy,
-    a practical ceiling beside the published peak."""
+    """HBM bytes per second of torch's plain device kernels on an nbytes
+    buffer: a copy (read + written, the mixed rate a copy gets), a sum (read
+    only) and a fill (written only) -- practical ceilings beside the
+    published peak."""
     src = torch.ones(nbytes // 8, dtype=torch.int64, device="cuda")
     dst = torch.empty_like(src)
-    for _ in range(3):
-        dst.copy_(src)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        dst.copy_(src)
-    e1.record()
-    e1.synchronize()
-    sec = e0.elapsed_time(e1) / 1e3 / reps
+    ops = {"copy": (lambda: dst.copy_(src), 2 * nbytes), "read": (lambda: src.sum(), nbytes),
+           "write": (lambda: dst.fill_(3), nbytes)}
+    out = {}
+    for name, (op, moved) in ops.items():
+        for _ in range(3):
+            op()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            op()
+        e1.record()
+        e1.synchronize()
+        out[name] = moved / (e0.elapsed_time(e1) / 1e3 / reps)
     del src, dst
     torch.cuda.empty_cache()
-    return 2 * nbytes / sec
+    return out
 
 
 def bench_ensemble(torch, P, n=4096, solo_per_L=3, tune_scale=10, serving=True, solo=True):
@@ -471,9 +476,12 @@ def main():
     })
     # the counted traffic of the pass against what a plain device copy of
     # 1 GiB moves per second on this GPU (reads and writes mixed, as in the pass)
-    copy_gbs = device_copy_rate(torch) / 1e9
+    rates = device_copy_rate(torch)
+    copy_gbs = rates["copy"] / 1e9
     roofline["device_copy"] = {"GBps": round(copy_gbs, 1), "bytes_per_copy": 2 * 2**30,
-                               "note": "torch copy_ of 1 GiB, read + written"}
+                               "note": "torch copy_ of 1 GiB, read + written",
+                               "read_only_GBps": round(rates["read"] / 1e9, 1),
+                               "write_only_GBps": round(rates["write"] / 1e9, 1)}
     if roofline.get("traffic"):
         counted = roofline["traffic"] / (avg_ms / 1e3) / 1e9
         roofline["device_copy"].update({"pass_counted_GBps": round(counted, 1),
