@@ -84,6 +84,21 @@ def _valu_per_update(tag):
     return c["valu_lane_instructions_per_site_update"]
 
 
+def _hbm_per_update(tag):
+    """Counted HBM bytes per site update of the path's kernel (FETCH_SIZE and
+    WRITE_SIZE scaled by a device copy's counts), if they were taken and the
+    kernel sources are unchanged since."""
+    try:
+        with open(VALU_COUNTERS) as f:
+            c = json.load(f)[tag]
+    except (OSError, ValueError, KeyError):
+        return None
+    files = [os.path.join(ROOT, s) for s in c["sources"]]
+    if c.get("sources_sha256") != _sha(files) or "hbm_bytes_per_dispatch" not in c:
+        return None
+    return c["hbm_bytes_per_dispatch"] / c["site_updates_per_dispatch"]
+
+
 def pass_roofline(alg_bytes, avg_ms, counters):
     """The pass kernel against HBM (algorithmic bytes per launch over the
     launch time) and, when rocprofv3 counted its VALU instructions per launch
@@ -530,6 +545,13 @@ def main():
                 "bound": "alu", "achieved": pv["value"] * per_update, "peak": VALU_LANE_OPS,
                 "unit": "VALU lane instructions/s", "frac": round(pv["value"] * per_update / VALU_LANE_OPS, 4),
                 "valu_lane_instructions_per_site_update": per_update}
+        # the p = 1/2 pass's counted HBM traffic beside its VALU roof
+        bpu = _hbm_per_update("half")
+        if bpu is not None and paths[HEADLINE_HALF.name]["roofline"] is not None:
+            gbs = paths[HEADLINE_HALF.name]["value"] * bpu / 1e9
+            paths[HEADLINE_HALF.name]["roofline"]["hbm"] = {
+                "counted_GBps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                "bytes_per_site_update": round(bpu, 5), "over_device_copy": round(gbs / copy_gbs, 4)}
         paths[PERSITE.name]["philox_only_blocks_per_s"] = P.philox_rate()
         out["paths"] = paths
 

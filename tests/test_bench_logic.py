@@ -50,3 +50,14 @@ def test_cpu_baseline_helpers():
     r = bench.oracle_rate(256, 256, 1.0, 0.0, 42, 64, 0.05, threads=1)
     assert r["cores"] == 1 and r["kind"] == "oracle" and r["value"] > 0 and "1 thread" in r["sample"]
     assert isinstance(bench.cpu_model(), str) and bench.cpu_model()
+
+
+def test_counted_bytes_of_the_half_pass_match_its_pass_model():
+    """The p = 1/2 pass's counted HBM bytes per site update lie between the
+    algorithmic figure (the state read and written once per 4-MCS pass, 1/8
+    byte per site update) and that figure with the whole band halo read
+    twice (reads 1.25 x for 8 halo rows above and below a 128-row band)."""
+    bpu = bench._hbm_per_update("half")
+    if bpu is None:  # counters taken on other kernel sources: not reported
+        return
+    assert 0.125 <= bpu <= 0.125 * (1 + 0.25) / 2 + 0.125 / 2 + 1e-9
