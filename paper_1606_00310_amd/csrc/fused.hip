@@ -59,10 +59,10 @@ void fused_kernel_name(const SweepArgs& a, XiMode mode, bool has_q, int32_t dept
         return;
     }
     // mask passes: what the instantiation knows of the number of draws (an
-    // odd one without removals carries the shared last draw between a row's
-    // half-steps)
+    // odd one carries the shared last draw between a row's half-steps, except
+    // with removals at two words per lane)
     const bool rnd = mode == XiMode::Mask && !draw_free;
-    const char* odd = !rnd ? "" : ((a.ndraw & 1) == 0 ? ",Even" : (has_q ? ",Any" : ",OddTail"));
+    const char* odd = !rnd ? "" : ((a.ndraw & 1) == 0 ? ",Even" : ((has_q && a.W == 1024) ? ",Any" : ",OddTail"));
     if (a.W == 1024) {
         if (depth == kLdsDepth && draw_free) std::snprintf(out, n, "mcs_block_lds_kernel<16,%d,%s>", depth, q);
         else std::snprintf(out, n, "mcs_block_kernel<8,2,%d,%s,%s%s>", depth, m, q, odd);

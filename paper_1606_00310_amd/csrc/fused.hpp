@@ -171,9 +171,12 @@ __device__ __forceinline__ void window_halfstep(const SweepArgs& ah, int rr, int
 
 // DR (mask mode): what the launch knows of the number of draws; with
 // Draws::OddTail each row's even half-step hands the shared last draw to its
-// odd one (mask_words).
+// odd one (mask_words), and with removals (HASQ) at one word per lane the
+// kernel is bounded to four waves per SIMD (128 VGPRs), which keeps two
+// 512-thread workgroups per CU.
 template <int NW, int I, int K, XiMode MODE, bool HASQ, Draws DR = Draws::Any>
-__global__ __launch_bounds__(NW * 64) void mcs_block_kernel(SweepArgs a, const uint64_t* src, uint64_t* dst,
+__global__ __launch_bounds__(NW * 64, (DR == Draws::OddTail && HASQ && I == 1) ? 4 : 1) void mcs_block_kernel(
+    SweepArgs a, const uint64_t* src, uint64_t* dst,
                                                             int32_t band)
 {
     constexpr int H = 2 * K;      // half-steps per pass
@@ -832,12 +835,14 @@ hipError_t launch_block(const SweepArgs& a, XiMode mode, bool has_q, const uint6
         }
     } else if (mode == XiMode::Mask) {
         if constexpr (K <= kMaxDepthMask) {
-            // an odd number of draws without removals (p = 1/2 among them): one
-            // Philox call per word serves both half-steps of the last draw (with
-            // removals the words kept between the half-steps would cost the
-            // 4-MCS pass its second workgroup per CU)
+            // an odd number of draws (p = 1/2 among them): one Philox call per
+            // word serves both half-steps of the last draw.  With removals the
+            // kept words need a bound of four waves per SIMD to keep the 4-MCS
+            // pass at two workgroups per CU (128 VGPRs, two spilled); at two
+            // words per lane they would not fit, and the odd half-step calls again.
             const bool odd = (a.ndraw & 1) != 0;
-            if (has_q && odd) hipLaunchKernelGGL((mcs_block_kernel<NW, I, K, XiMode::Mask, true, Draws::Any>), grid, block, 0, stream, a, src, dst, band);
+            constexpr Draws ODD_Q = I == 1 ? Draws::OddTail : Draws::Any;
+            if (has_q && odd) hipLaunchKernelGGL((mcs_block_kernel<NW, I, K, XiMode::Mask, true, ODD_Q>), grid, block, 0, stream, a, src, dst, band);
             else if (has_q) hipLaunchKernelGGL((mcs_block_kernel<NW, I, K, XiMode::Mask, true, Draws::Even>), grid, block, 0, stream, a, src, dst, band);
             else if (odd) hipLaunchKernelGGL((mcs_block_kernel<NW, I, K, XiMode::Mask, false, Draws::OddTail>), grid, block, 0, stream, a, src, dst, band);
             else hipLaunchKernelGGL((mcs_block_kernel<NW, I, K, XiMode::Mask, false, Draws::Even>), grid, block, 0, stream, a, src, dst, band);

@@ -51,7 +51,7 @@ def rough_state(orc, X, Y, seed, n=4):
 PHASES = [(1.0, 0.0), (0.0, 1.0), (1.0, 1.0), (0.0, 0.0)]
 
 
-def run_phases(orc, sca, X, Y, depth, band, seed, n, phases=PHASES, expect_depth=None):
+def run_phases(orc, sca, X, Y, depth, band, seed, n, phases=PHASES, expect_depth=None, path=0):
     st = rough_state(orc, X, Y, seed)
     lat = sca.Lattice(X, Y, seed=seed)
     lat.restore(snapshot_of(orc, st, lat.device), st.t)
@@ -60,7 +60,7 @@ def run_phases(orc, sca, X, Y, depth, band, seed, n, phases=PHASES, expect_depth
         plan = lat.plan(n, p, q)
         _say(f"  phase p={p} q={q} n={n}: {plan['n_pass']} x {plan['kernel']}, tails {plan['tail1']}+"
              f"{plan['tail2']} ({plan['tail_kernel']})")
-        assert plan["path"] == 0 and plan["band"] == band
+        assert plan["path"] == path and plan["band"] == band
         if expect_depth is not None:
             assert plan["depth"] == (expect_depth if plan["n_pass"] else 0)
         lat.step(n, p, q)
@@ -150,7 +150,7 @@ def test_reset_and_plan(orc, sca):
     # one draw (odd): the instantiation that keeps the shared draw between a row's half-steps
     assert half["kernel"] == "mcs_block_kernel<8,1,4,Mask,false,OddTail>"
     assert lat.plan(200, 0.9375, 0.0)["kernel"] == "mcs_block_kernel<8,1,4,Mask,false,Even>"
-    assert lat.plan(200, 0.5, 0.5)["kernel"] == "mcs_block_kernel<8,1,4,Mask,true,Any>"
+    assert lat.plan(200, 0.5, 0.5)["kernel"] == "mcs_block_kernel<8,1,4,Mask,true,OddTail>"
     assert lat.plan(200, 0.75, 0.25)["kernel"] == "mcs_block_kernel<8,1,4,Mask,true,Even>"
     ps = lat.plan(10, 0.93, 0.07)
     assert (ps["path"], ps["n_pass"], ps["n_unfused"]) == (2, 0, 10)
@@ -186,3 +186,19 @@ def test_blocked_pass_needs_the_pass_buffer(sca):
     small = torch.empty(10, dtype=torch.int64, device=lat.device)
     assert L.lib().sca_set_pass_buffer(lat._ctx, small.data_ptr(), 80) == L.SCA_EINVAL
     assert L.lib().sca_set_pass_buffer(lat._ctx, lat.slopes.data_ptr(), lat.slopes.numel() * 8) == L.SCA_EINVAL
+
+
+# Random-word passes with an odd number of draws (one Philox call per word and
+# MCS, the even half-step keeps the shared draw for the odd one), with and
+# without removals, from a rough state: 1..4 MCS per pass at one, two and
+# eight waves per row, and at two words per lane (X = 2^17, where removals
+# recompute the shared call).
+ODD_DRAWS = [(0.5, 0.5), (0.625, 0.125), (0.5, 0.0), (0.34375, 0.0), (0.5, 0.25)]
+
+
+@pytest.mark.parametrize("X,Y,depth,band", [(8192, 64, 4, 32), (16384, 32, 3, 16), (65536, 64, 4, 32),
+                                            (65536, 32, 2, 16), (131072, 32, 4, 16), (65536, 128, 1, 32)])
+def test_odd_draw_passes_from_rough_state(orc, sca, X, Y, depth, band):
+    _say(f"[blocked] odd draw counts X={X} Y={Y} depth={depth} band={band}")
+    run_phases(orc, sca, X, Y, depth, band, seed=7001 + depth, n=2 * depth + 3, phases=ODD_DRAWS,
+               expect_depth=depth, path=1)
